@@ -1,0 +1,264 @@
+/*
+ * CPU oracle for Strassen's block-recursive matrix inversion.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library and is deliberately plain:
+ * double precision throughout, no blocking, no fusion, no reordering beyond
+ * what the definitions below state, built with -ffp-contract=off so that
+ * every a - b*c is a rounded product followed by a rounded difference.
+ *
+ * Storage: every matrix is column-major with a leading dimension, the layout
+ * of the paper's matrix blocks (Sec. 3.2, "Block Matrix Data Structure").
+ *
+ * Functions
+ *   oracle_gemm          C = A * B, plain triple loop, k summed in ascending
+ *                        order (the definition of the matrix product that the
+ *                        paper's `multiply` computes, Sec. 3.3).
+ *   oracle_gj_inv        O1: Gauss-Jordan elimination on [A | I] with partial
+ *                        pivoting (one concrete choice for the leaf inversion,
+ *                        which the paper leaves open: Alg. 1, "invert A in any
+ *                        approach").
+ *   oracle_strassen_inv  O2: Strassen's inversion scheme, Alg. 1 (Sec. 3.1),
+ *                        in its literal form: I = A11^-1, II = A21 I,
+ *                        III = I A12, IV = A21 III, V = IV - A22, VI = V^-1,
+ *                        C12 = III VI, C21 = VI II, VII = III C21,
+ *                        C11 = I - VII, C22 = -VI; recursion stops at the
+ *                        leaf threshold and inverts the leaf with O1.
+ *   oracle_ns_step       one Newton(-Schulz) refinement step
+ *                        X' = X + X (I - A X) (Sec. 2.1 cites Newton iteration
+ *                        as the stabiliser of Strassen inversion).
+ *
+ * Readings of the paper that this file fixes (the paper is silent):
+ *   - leaf test: recurse while m > leaf, invert when m <= leaf (Alg. 1 tests
+ *     n = threshold, Alg. 2 tests size/blockSize = 1; both only consider
+ *     n = 2^p, Sec. 4);
+ *   - split of an order-m block when m is not leaf * 2^k: the leading block
+ *     has order n1 = 64 * ceil(m / 128) for m >= 128 and ceil(m / 2) below;
+ *     this is exact halving whenever m = leaf * 2^k with leaf a multiple of 64
+ *     (or any power of two);
+ *   - pivot choice: largest |entry| in the pivot column at or below the
+ *     diagonal, ties to the smallest row index; an exactly zero or
+ *     non-finite pivot column stops the elimination and reports the 1-based
+ *     column (LAPACK getrf convention).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define AT(p, i, j, ld) ((p)[(int64_t)(i) + (int64_t)(j) * (int64_t)(ld)])
+
+int oracle_version(void) { return 1; }
+
+/* C (m x n, ldc) = A (m x k, lda) * B (k x n, ldb). */
+void oracle_gemm(const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double *C, int64_t ldc, int64_t m, int64_t n, int64_t k)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i)
+            AT(C, i, j, ldc) = 0.0;
+        /* For every (i, j) the terms are added in ascending k. */
+        for (int64_t p = 0; p < k; ++p) {
+            const double b = AT(B, p, j, ldb);
+            for (int64_t i = 0; i < m; ++i)
+                AT(C, i, j, ldc) = AT(C, i, j, ldc) + AT(A, i, p, lda) * b;
+        }
+    }
+}
+
+/* O1.  X (n x n, ldx) = A^-1 by Gauss-Jordan on the augmented [A | I].
+ * Returns 0, or k+1 when the pivot column k (0-based) holds no usable pivot
+ * (all candidates zero, or any candidate non-finite); X is then unspecified. */
+int oracle_gj_inv(const double *A, int64_t n, int64_t lda, double *X, int64_t ldx)
+{
+    if (n <= 0)
+        return 0;
+    const int64_t w = 2 * n; /* columns of [A | I] */
+    double *M = (double *)malloc(sizeof(double) * (size_t)(n * w));
+    double *f = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!M || !f) {
+        free(M);
+        free(f);
+        return -1;
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < n; ++i) {
+            AT(M, i, j, n) = AT(A, i, j, lda);
+            AT(M, i, n + j, n) = (i == j) ? 1.0 : 0.0;
+        }
+
+    int info = 0;
+    for (int64_t k = 0; k < n && !info; ++k) {
+        /* partial pivoting: largest |M[i,k]| for i >= k, smallest i on ties */
+        int64_t p = k;
+        double best = fabs(AT(M, k, k, n));
+        int finite = isfinite(AT(M, k, k, n));
+        for (int64_t i = k + 1; i < n; ++i) {
+            const double v = fabs(AT(M, i, k, n));
+            if (!isfinite(v))
+                finite = 0;
+            if (v > best) {
+                best = v;
+                p = i;
+            }
+        }
+        if (!finite || !(best > 0.0)) {
+            info = (int)(k + 1);
+            break;
+        }
+        if (p != k)
+            for (int64_t j = 0; j < w; ++j) {
+                const double t = AT(M, k, j, n);
+                AT(M, k, j, n) = AT(M, p, j, n);
+                AT(M, p, j, n) = t;
+            }
+        /* scale the pivot row: every entry divided by the pivot */
+        const double piv = AT(M, k, k, n);
+        for (int64_t j = 0; j < w; ++j)
+            AT(M, k, j, n) = AT(M, k, j, n) / piv;
+        /* eliminate column k from every other row:
+         * row_i <- row_i - M[i,k] * row_k, with M[i,k] taken before the step */
+        for (int64_t i = 0; i < n; ++i)
+            f[i] = AT(M, i, k, n);
+#pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < w; ++j) {
+            const double rk = AT(M, k, j, n);
+            for (int64_t i = 0; i < n; ++i)
+                if (i != k)
+                    AT(M, i, j, n) = AT(M, i, j, n) - f[i] * rk;
+        }
+    }
+    if (!info)
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                AT(X, i, j, ldx) = AT(M, i, n + j, n);
+    free(M);
+    free(f);
+    return info;
+}
+
+/* Order of the leading block when an order-m block is split. */
+int64_t oracle_split(int64_t m)
+{
+    if (m >= 128)
+        return 64 * ((m + 127) / 128);
+    return (m + 1) / 2;
+}
+
+static double *dalloc(int64_t r, int64_t c)
+{
+    size_t cnt = (size_t)((r > 0 ? r : 1) * (c > 0 ? c : 1));
+    return (double *)malloc(sizeof(double) * cnt);
+}
+
+/* Copy / negate / subtract helpers on (r x c) column-major views. */
+static void mat_sub(const double *P, int64_t ldp, const double *Q, int64_t ldq,
+                    double *R, int64_t ldr, int64_t r, int64_t c)
+{
+    for (int64_t j = 0; j < c; ++j)
+        for (int64_t i = 0; i < r; ++i)
+            AT(R, i, j, ldr) = AT(P, i, j, ldp) - AT(Q, i, j, ldq);
+}
+
+static void mat_neg(const double *P, int64_t ldp, double *R, int64_t ldr, int64_t r, int64_t c)
+{
+    for (int64_t j = 0; j < c; ++j)
+        for (int64_t i = 0; i < r; ++i)
+            AT(R, i, j, ldr) = -AT(P, i, j, ldp);
+}
+
+static void mat_copy(const double *P, int64_t ldp, double *R, int64_t ldr, int64_t r, int64_t c)
+{
+    for (int64_t j = 0; j < c; ++j)
+        for (int64_t i = 0; i < r; ++i)
+            AT(R, i, j, ldr) = AT(P, i, j, ldp);
+}
+
+/* O2, Alg. 1.  C (m x m, ldc) = A^-1.  col0 is the global column offset of
+ * this block, so that a failing leaf reports a global 1-based column. */
+static int strassen_rec(const double *A, int64_t m, int64_t lda, double *C, int64_t ldc,
+                        int64_t leaf, int64_t col0)
+{
+    if (m <= leaf) {
+        int info = oracle_gj_inv(A, m, lda, C, ldc);
+        return info > 0 ? (int)(info + col0) : info;
+    }
+    const int64_t n1 = oracle_split(m), n2 = m - n1;
+    const double *A11 = &AT(A, 0, 0, lda), *A12 = &AT(A, 0, n1, lda);
+    const double *A21 = &AT(A, n1, 0, lda), *A22 = &AT(A, n1, n1, lda);
+    double *C11 = &AT(C, 0, 0, ldc), *C12 = &AT(C, 0, n1, ldc);
+    double *C21 = &AT(C, n1, 0, ldc), *C22 = &AT(C, n1, n1, ldc);
+
+    double *I = dalloc(n1, n1), *II = dalloc(n2, n1), *III = dalloc(n1, n2);
+    double *IV = dalloc(n2, n2), *V = dalloc(n2, n2), *VI = dalloc(n2, n2);
+    double *VII = dalloc(n1, n1);
+    int info = -1;
+    if (!I || !II || !III || !IV || !V || !VI || !VII)
+        goto done;
+
+    info = strassen_rec(A11, n1, lda, I, n1, leaf, col0);      /* I   = A11^-1   */
+    if (info)
+        goto done;
+    oracle_gemm(A21, lda, I, n1, II, n2, n2, n1, n1);           /* II  = A21 I    */
+    oracle_gemm(I, n1, A12, lda, III, n1, n1, n2, n1);          /* III = I A12    */
+    oracle_gemm(A21, lda, III, n1, IV, n2, n2, n2, n1);         /* IV  = A21 III  */
+    mat_sub(IV, n2, A22, lda, V, n2, n2, n2);                   /* V   = IV - A22 */
+    info = strassen_rec(V, n2, n2, VI, n2, leaf, col0 + n1);    /* VI  = V^-1     */
+    if (info)
+        goto done;
+    oracle_gemm(III, n1, VI, n2, C12, ldc, n1, n2, n2);         /* C12 = III VI   */
+    oracle_gemm(VI, n2, II, n2, C21, ldc, n2, n1, n2);          /* C21 = VI II    */
+    oracle_gemm(III, n1, C21, ldc, VII, n1, n1, n1, n2);        /* VII = III C21  */
+    mat_sub(I, n1, VII, n1, C11, ldc, n1, n1);                  /* C11 = I - VII  */
+    mat_neg(VI, n2, C22, ldc, n2, n2);                          /* C22 = -VI      */
+done:
+    free(I);
+    free(II);
+    free(III);
+    free(IV);
+    free(V);
+    free(VI);
+    free(VII);
+    return info;
+}
+
+int oracle_strassen_inv(const double *A, int64_t n, int64_t lda, double *X, int64_t ldx,
+                        int64_t leaf)
+{
+    if (n <= 0)
+        return 0;
+    if (leaf < 1)
+        return -2;
+    return strassen_rec(A, n, lda, X, ldx, leaf, 0);
+}
+
+/* One refinement step: Xn = X + X (I - A X). */
+int oracle_ns_step(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
+                   double *Xn, int64_t ldxn)
+{
+    double *AX = dalloc(n, n), *R = dalloc(n, n), *XR = dalloc(n, n);
+    int rc = -1;
+    if (AX && R && XR) {
+        oracle_gemm(A, lda, X, ldx, AX, n, n, n, n);
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                AT(R, i, j, n) = ((i == j) ? 1.0 : 0.0) - AT(AX, i, j, n);
+        oracle_gemm(X, ldx, R, n, XR, n, n, n, n);
+        for (int64_t j = 0; j < n; ++j)
+            for (int64_t i = 0; i < n; ++i)
+                AT(Xn, i, j, ldxn) = AT(X, i, j, ldx) + AT(XR, i, j, n);
+        rc = 0;
+    }
+    free(AX);
+    free(R);
+    free(XR);
+    return rc;
+}
+
+/* Copy used by tests that build matrices from views. */
+void oracle_copy(const double *P, int64_t ldp, double *R, int64_t ldr, int64_t r, int64_t c)
+{
+    mat_copy(P, ldp, R, ldr, r, c);
+}

@@ -1,0 +1,91 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies the oracle source, plants one plausible mistake (a dropped
+term, a flipped sign, a transposed operand, a missing row swap, an index
+slip), compiles the mutant into a temporary library and checks that at least
+one pin fails against it.  The unmodified source must pass the same checks.
+Everything runs on the CPU.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle.exact import exact_inverse, to_float
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "spin_oracle.c")
+
+MUTANTS = {
+    "c22_sign": ("mat_neg(VI, n2, C22, ldc, n2, n2);", "mat_copy(VI, n2, C22, ldc, n2, n2);"),
+    "schur_sign": ("mat_sub(IV, n2, A22, lda, V, n2, n2, n2);", "mat_sub(A22, lda, IV, n2, V, n2, n2, n2);"),
+    "ii_transposed": ("oracle_gemm(A21, lda, I, n1, II, n2, n2, n1, n1);",
+                      "oracle_gemm(I, n1, A21, lda, II, n2, n2, n1, n1);"),
+    "c11_dropped_term": ("mat_sub(I, n1, VII, n1, C11, ldc, n1, n1);", "mat_copy(I, n1, C11, ldc, n1, n1);"),
+    "c21_operand_order": ("oracle_gemm(VI, n2, II, n2, C21, ldc, n2, n1, n2);",
+                          "oracle_gemm(II, n2, VI, n2, C21, ldc, n2, n1, n2);"),
+    "no_row_swap": ("if (p != k)\n            for", "if (0)\n            for"),
+    "gemm_k_slip": ("for (int64_t p = 0; p < k; ++p) {", "for (int64_t p = 1; p < k; ++p) {"),
+    "scale_left_half_only": ("for (int64_t j = 0; j < w; ++j)\n            AT(M, k, j, n) = AT(M, k, j, n) / piv;",
+                             "for (int64_t j = 0; j < n; ++j)\n            AT(M, k, j, n) = AT(M, k, j, n) / piv;"),
+    "eliminate_below_only": ("if (i != k)\n                    AT(M, i, j, n)", "if (i > k)\n                    AT(M, i, j, n)"),
+    "second_leaf_offset": ("col0 + n1);    /* VI", "col0);    /* VI"),
+}
+
+
+def _pins_pass(lib) -> bool:
+    """A compact set of the pins from test_oracle_pins; True iff all hold."""
+    ok = True
+    # exact unimodular inverse through both programs
+    A = W.unimodular_bidiag(32, seed=5)
+    ref = to_float(exact_inverse(A))
+    X1, i1 = oracle.gj_inv(A, lib)
+    X2, i2 = oracle.strassen_inv(A, 8, lib)
+    ok &= i1 == 0 and i2 == 0 and np.array_equal(X1, ref) and np.array_equal(X2, ref)
+    # permutation (pivoting)
+    P = W.permutation(9, seed=2)
+    Xp, ip = oracle.gj_inv(P, lib)
+    ok &= ip == 0 and np.array_equal(Xp, P.T)
+    # agreement with LAPACK on a non-symmetric matrix, both programs
+    B = W.diag_dominant(128, seed=1) - 100.0 * np.eye(128)
+    ref = np.linalg.inv(B)
+    for X, info in (oracle.gj_inv(B, lib), oracle.strassen_inv(B, 32, lib)):
+        ok &= info == 0 and np.linalg.norm(X - ref) / np.linalg.norm(ref) < 1e-12
+    # gemm on integers
+    g = np.random.default_rng(0)
+    M = g.integers(-9, 9, size=(7, 5)).astype(np.float64)
+    N = g.integers(-9, 9, size=(5, 6)).astype(np.float64)
+    ok &= np.array_equal(oracle.gemm(M, N, lib), M @ N)
+    # breakdown column reporting: a zero column in the second leaf
+    S = W.diag_dominant(64, seed=8)
+    S[:, 40] = 0.0
+    S[40, :] = 0.0
+    _, info = oracle.strassen_inv(S, 32, lib)
+    ok &= info == 41
+    return bool(ok)
+
+
+def _build_variant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    path = tmp_path / f"mut_{name}.c"
+    path.write_text(src.replace(old, new))
+    out = str(tmp_path / f"libmut_{name}.so")
+    oracle.build(str(path), out)
+    return oracle.load(out)
+
+
+def test_unmutated_passes(tmp_path):
+    path = tmp_path / "same.c"
+    path.write_text(open(SRC).read())
+    out = str(tmp_path / "libsame.so")
+    oracle.build(str(path), out)
+    assert _pins_pass(oracle.load(out))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    lib = _build_variant(tmp_path, name, old, new)
+    assert not _pins_pass(lib), f"mutant {name} survived the oracle pins"
