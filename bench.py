@@ -1,0 +1,214 @@
+"""Benchmark: Strassen block-recursive inversion on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--n N] [--leaf L] [--kind spd|dd|spdk]
+                    [--mode fp64|fp32] [--ns-steps S] [--no-cpu] [--no-trace]
+
+Default workload: FP64 inversion of the SPD matrix A = B B^T / n + I
+(B i.i.d. N(0, 1), seed 2), n = 8192, leaf 256 (recursion depth 5).  A step
+is one complete inversion (every level of the recursion, every leaf) with A
+already resident in HBM.  The metric is 2 n^3 / t (the method's exact flop
+count) in TFLOP/s, with its fraction of the FP64 matrix-core peak.
+
+Prints one JSON line.  Extra fields:
+  roofline     -- dominant kernel (largest total time in a traced replay of
+                  the same steps, HIP events on the launch stream): its
+                  algorithmic flops per launch / average launch duration,
+                  against the FP64 MFMA peak;
+  cpu_baseline -- the CPU oracle (literal Alg. 1 recursion, OpenMP) timed on a
+                  bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 matrix-core peak
+PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix-core peak
+METRIC = "inversion TFLOP/s (2n³/t) & % of MFMA peak; p50/p99 latency under load"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--n", type=int, default=8192)
+    p.add_argument("--leaf", type=int, default=256)
+    p.add_argument("--kind", default="spd", choices=["spd", "dd", "spdk"])
+    p.add_argument("--mode", default="fp64", choices=["fp64", "fp32"])
+    p.add_argument("--ns-steps", type=int, default=2)
+    p.add_argument("--seed", type=int, default=None)
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-trace", action="store_true")
+    p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU oracle work")
+    return p.parse_args()
+
+
+def make_input(kind: str, n: int, seed: int):
+    import workloads as W
+    if kind == "spd":
+        return W.spd_gram(n, seed), f"spd_gram (B B^T/n + I, B ~ N(0,1)), seed {seed}"
+    if kind == "dd":
+        return W.diag_dominant(n, seed), f"diag_dominant (U(-1,1) + n I), seed {seed}"
+    return W.spd_spectrum(n, seed, 1e4), f"spd_spectrum (Q diag(lam) Q^T, kappa 1e4), seed {seed}"
+
+
+def cpu_baseline(kind: str, leaf: int, seed: int, budget_s: float):
+    """Time the oracle's literal Strassen recursion on the host cores, on a
+    bounded sample (a smaller matrix of the same class and leaf size)."""
+    import oracle
+    lib = oracle.load()
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate on n = 1024, then take the largest sample that fits the budget
+    a, _ = make_input(kind, 1024, seed)
+    t0 = time.perf_counter()
+    oracle.strassen_inv(a, min(leaf, 1024), lib)
+    t_cal = time.perf_counter() - t0
+    n_s = 1024
+    for cand in (1536, 2048, 3072, 4096):
+        if t_cal * (cand / 1024) ** 3 <= budget_s:
+            n_s = cand
+    if n_s == 1024:
+        t = t_cal
+    else:
+        a, _ = make_input(kind, n_s, seed)
+        t0 = time.perf_counter()
+        _, info = oracle.strassen_inv(a, min(leaf, n_s), lib)
+        t = time.perf_counter() - t0
+    return {
+        "value": 2.0 * n_s ** 3 / t / 1e12,
+        "unit": "TFLOP/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"oracle Strassen recursion (Alg. 1, FP64, OpenMP) on {kind} n={n_s} "
+                  f"leaf={min(leaf, n_s)}: one run, {t:.2f} s",
+    }
+
+
+def roofline_from_trace(recs, n_steps: int):
+    """Dominant kernel = largest total traced time; achieved = its algorithmic
+    flops per launch / its average launch duration."""
+    by = {}
+    for r in recs:
+        d = by.setdefault(r["kernel"], {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "count": 0})
+        d["ms"] += r["ms"]
+        d["flops"] += r["flops"]
+        d["bytes"] += r["bytes"]
+        d["count"] += 1
+    name, d = max(by.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = d["ms"] / d["count"]
+    flops_per_launch = d["flops"] / d["count"]
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_FP64_TFLOPS if "f64" in name or "leaf" in name else PEAK_FP32_TFLOPS
+    breakdown = {k: {"ms_per_step": round(v["ms"] / n_steps, 4), "launches_per_step": v["count"] // n_steps,
+                     "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3)}
+                 for k, v in sorted(by.items(), key=lambda kv: -kv[1]["ms"])}
+    return {
+        "bound": "mfma",
+        "kernel": name,
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "avg_launch_ms": round(avg_ms, 5),
+        "flops_per_launch": flops_per_launch,
+        "launches": d["count"],
+    }, breakdown
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   f"--gpus {args.gpus} is not supported (use --gpus 1)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1801_04723_amd as spin
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    seed = args.seed if args.seed is not None else {"spd": 2, "dd": 3, "spdk": 4}[args.kind]
+    n, leaf = args.n, args.leaf
+    a_host, desc = make_input(args.kind, n, seed)
+    import numpy as np
+    dA = torch.from_numpy(np.ascontiguousarray(a_host.T)).to(dev).t()  # column-major on device
+    del a_host
+    dX = torch.empty_like(dA)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        if args.mode == "fp64":
+            spin.invert(dA, leaf=leaf, out=dX)
+        else:
+            spin.invert_mixed(dA, leaf=leaf, mode="fp32", ns_steps=args.ns_steps, out=dX)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(args.steps):
+        step()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop) / args.steps
+    status = spin.info()
+    value = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    rho = spin.residual(dA, dX)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.mode == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{desc}, n={n}, leaf={leaf}, {args.mode}"
+                        + (f", {args.ns_steps} Newton steps" if args.mode != "fp64" else ""),
+            "n": n, "leaf": leaf, "mode": args.mode,
+            "depth": max(0, (n // leaf).bit_length() - 1) if n > leaf else 0,
+        },
+        "pct_fp64_peak": round(100.0 * value / PEAK_FP64_TFLOPS, 2),
+        "rho": rho,
+        "status": status,
+        "wall_s_timed": round(wall, 4),
+    }
+    if not args.no_trace:
+        spin.trace_enable(True)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        spin.trace_enable(False)
+        recs = spin.trace_collect()
+        roof, breakdown = roofline_from_trace(recs, args.steps)
+        out["roofline"] = roof
+        out["kernel_breakdown"] = breakdown
+    else:
+        out["roofline"] = None
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.kind, leaf, seed, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

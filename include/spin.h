@@ -1,0 +1,185 @@
+/*
+ * spin.h -- C ABI of the MI355X (gfx950) Strassen block-recursive inverter.
+ *
+ * The library inverts dense square matrices with Strassen's inversion scheme
+ * (Alg. 1, Sec. 3.1 of "SPIN: A Fast and Scalable Matrix Inversion Method in
+ * Apache Spark"; the recursive block form is Alg. 2, Sec. 3.3):
+ *
+ *     [A11 A12]^-1   [C11 C12]      I = A11^-1, II = A21 I, III = I A12,
+ *     [A21 A22]    = [C21 C22]      V = A21 III - A22, VI = V^-1,
+ *                                   C12 = III VI, C21 = VI II,
+ *                                   C11 = I - III C21, C22 = -VI,
+ *
+ * recursing on A11 and on the Schur complement until a block has order at most
+ * `leaf`, which is inverted directly (the paper allows any method there; this
+ * library uses Gauss-Jordan elimination with partial pivoting in FP64).
+ *
+ * Conventions shared by every entry point
+ *   Layout     column-major with a leading dimension, as the paper stores its
+ *              matrix blocks (Sec. 3.2).  `Ainv` uses its own leading dimension
+ *              `ldx` (>= n).  A row-major caller may pass its buffers unchanged:
+ *              the transpose of the inverse is the inverse of the transpose, so
+ *              a row-major A yields the row-major inverse.
+ *   Memory     A, Ainv: device pointers owned by the caller.  A is never
+ *              written; A and Ainv must not overlap (SPIN_E_ALIAS).  The
+ *              library owns a per-stream workspace, allocated on first use,
+ *              kept for reuse and freed by spin_release().
+ *   Streams    every compute call is enqueued on `stream` (0 = the null
+ *              stream) and returns before the GPU finishes.  Calls on one
+ *              stream are ordered; calls from several host threads must use
+ *              different streams.
+ *   Errors     the return value is an argument or resource status known at
+ *              enqueue time: 0 = enqueued, negative = SPIN_E_* (nothing was
+ *              enqueued).  The numerical status (a zero or non-finite leaf
+ *              pivot, refinement divergence) is written by the GPU and read by
+ *              spin_info() after the work completes.
+ */
+#ifndef SPIN_H
+#define SPIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
+
+/* ---- status codes --------------------------------------------------------- */
+#define SPIN_OK 0
+#define SPIN_E_NULL (-1)      /* a required pointer is NULL                    */
+#define SPIN_E_N (-2)         /* n < 1 (or n beyond SPIN_MAX_N)                */
+#define SPIN_E_LD (-3)        /* a leading dimension is smaller than n         */
+#define SPIN_E_LEAF (-4)      /* leaf < 1 or leaf > SPIN_MAX_LEAF              */
+#define SPIN_E_ALIAS (-5)     /* A and Ainv overlap                            */
+#define SPIN_E_MODE (-6)      /* unknown precision mode or refinement count    */
+#define SPIN_E_COUNT (-7)     /* batch count < 0 or above SPIN_MAX_BATCH       */
+#define SPIN_E_NOMEM (-10)    /* device allocation of the workspace failed     */
+#define SPIN_E_HIP (-11)      /* a HIP runtime call or kernel launch failed    */
+/* numerical status (positive values come from spin_info / info arrays):      */
+/*   k > 0  : the pivot search for global column k (1-based) found only zero  */
+/*            or non-finite candidates; the inverse is unspecified.           */
+#define SPIN_NS_DIVERGED (-100) /* refinement residual did not decrease       */
+
+#define SPIN_MAX_LEAF 2048
+#define SPIN_MAX_N (1 << 20)
+#define SPIN_MAX_BATCH 65536
+
+/* precision modes */
+#define SPIN_FP64 0        /* every product and every leaf in FP64            */
+#define SPIN_MIXED_FP32 1  /* block products in FP32 (FP32 MFMA, FP32 accumulation),
+                              FP64 leaves, FP64 Newton refinement              */
+
+/* ---- FP64 inversion ------------------------------------------------------- */
+/* Ainv (n x n, ldx) := A^-1 for A (n x n, lda), FP64 throughout.
+ * Alg. 1 / Alg. 2; blocks of order <= leaf are inverted by Gauss-Jordan with
+ * partial pivoting.  Leading blocks and Schur complements must be
+ * nonsingular (true for SPD and strictly diagonally dominant A); otherwise the
+ * leaf that meets a zero pivot column reports it through spin_info(). */
+int spin_invert(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                int64_t leaf, spin_stream_t stream);
+
+/* ---- mixed-precision inversion with Newton refinement --------------------- */
+typedef struct spin_report {
+    double rho_before;   /* |A X0 - I|_F / (|A|_F |X0|_F) of the unrefined inverse */
+    double rho_after;    /* same after the refinement steps                         */
+    double r0_fro;       /* |I - A X0|_F                                            */
+    double r_fro[8];     /* |I - A X_k|_F before step k (k < steps)                 */
+    int steps;           /* refinement steps performed                              */
+    int status;          /* 0, k > 0 (pivot failure) or SPIN_NS_DIVERGED            */
+} spin_report;
+
+/* Ainv := A^-1 computed with the recursion's block products in the precision
+ * of `mode` (FP32 working copies of A and of the recursion's outputs) and FP64
+ * leaves, followed by `ns_steps` (0..8) FP64 Newton steps
+ *     R = I - A X,  X <- X + X R
+ * (Newton iteration as the stabiliser of Strassen inversion, Sec. 2.1).
+ * If `rep` is non-NULL the call waits for the stream, evaluates both residuals
+ * on the GPU and fills *rep; with rep == NULL the call is asynchronous and
+ * no residual is computed. */
+int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                      int64_t leaf, int mode, int ns_steps, spin_report *rep,
+                      spin_stream_t stream);
+
+/* ---- block product -------------------------------------------------------- */
+/* D (m x n, ldd) := alpha * A (m x k, lda) * B (k x n, ldb) + beta * C0 (m x n, ldc)
+ * plus the identity on the diagonal when add_identity != 0.  This is the
+ * paper's `multiply` (Sec. 3.3) with its `subtract` (Alg. 2) and the sign of
+ * `scalarMul` (Alg. 5) folded into the epilogue.  dtype SPIN_FP64: double
+ * operands and result, FP64 MFMA.  dtype SPIN_MIXED_FP32: float operands and
+ * result, FP32 MFMA with FP32 accumulation.  C0 may be NULL when beta == 0 and
+ * may equal D (each element is read before it is written); A and B must not
+ * overlap D.  Asynchronous on `stream`. */
+int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha,
+              const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
+              const void *C0, int64_t ldc, void *D, int64_t ldd, int add_identity,
+              spin_stream_t stream);
+
+/* ---- status and residual -------------------------------------------------- */
+/* Waits for `stream` and returns the numerical status of the last inversion
+ * enqueued on it: 0, k > 0 (1-based failing pivot column) or SPIN_NS_DIVERGED. */
+int spin_info(spin_stream_t stream);
+
+/* rho = |A X - I|_F / (|A|_F |X|_F) in FP64 on the GPU (the residual measure
+ * used to accept an inverse).  Waits for `stream`; writes *rho. */
+int spin_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
+                  double *rho, spin_stream_t stream);
+
+/* Bytes of library workspace one inversion of order n needs in `mode`. */
+size_t spin_workspace_bytes(int64_t n, int64_t leaf, int mode);
+
+/* Short static description of a status code. */
+const char *spin_strerror(int code);
+
+/* Frees every cached workspace and captured graph (waits for the device). */
+void spin_release(void);
+
+/* ---- schedule introspection (host only, no GPU needed) -------------------- */
+/* One step of the recursion schedule as the executor runs it (S-form: the
+ * Schur complement S = A22 - A21 A11^-1 A12 = -V is formed and inverted
+ * directly, so C22 = S^-1 and C12 = -III C22, C21 = -C22 II). */
+typedef struct spin_plan_op {
+    int kind;        /* 0 = group of block products, 1 = leaf inversion        */
+    int count;       /* products in the group (1 or 2); 1 for a leaf          */
+    int level;       /* recursion depth of the node that issues it            */
+    int pad_;
+    /* products: D = alpha * op_a * op_b + beta * C0 (+ I if add_identity)    */
+    int64_t m[2], n[2], k[2];
+    int a_buf[2], b_buf[2], c_buf[2], d_buf[2];  /* 0 = A, 1 = Ainv, 2 = workspace */
+    int64_t a_off[2], b_off[2], c_off[2], d_off[2]; /* element offsets           */
+    int64_t a_ld[2], b_ld[2], c_ld[2], d_ld[2];
+    double alpha[2], beta[2];
+    /* leaf: out (order L, at d_*[0]) := in^-1 (at a_*[0]); col0 = global column */
+    int64_t leaf_order, col0;
+} spin_plan_op;
+
+/* Writes up to `cap` steps of the schedule for (n, leaf) into ops[] (ops may
+ * be NULL with cap 0) and returns the total number of steps, or a negative
+ * SPIN_E_* code.  Element offsets refer to A (lda), Ainv (ldx) and a workspace
+ * of spin_plan_ws_elems(n, leaf) elements.  *flops (optional) receives the
+ * schedule's arithmetic count: 2 m n k per product, 2 L^3 per leaf. */
+int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
+                           spin_plan_op *ops, int64_t cap, double *flops);
+int64_t spin_plan_ws_elems(int64_t n, int64_t leaf);
+
+/* ---- per-kernel timing (for profiling; forces eager launches) ------------- */
+typedef struct spin_trace_rec {
+    char kernel[48];  /* kernel family and tile shape                           */
+    double ms;        /* HIP-event time of the launch on its stream             */
+    double flops;     /* algorithmic flops of the launch                        */
+    double bytes;     /* algorithmic HBM bytes of the launch (operands + result) */
+    int level;        /* recursion level (-1 outside the recursion)             */
+} spin_trace_rec;
+
+/* While enabled, inversions run eagerly (no graph replay) and every kernel
+ * launch is bracketed by HIP events on its stream. */
+int spin_trace_enable(int on);
+/* Waits for the traced work, copies up to `cap` records (returns the count
+ * available) and clears the trace buffer. */
+int64_t spin_trace_collect(spin_trace_rec *recs, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPIN_H */

@@ -1,0 +1,122 @@
+// Auxiliary bandwidth-bound kernels: status reset, precision conversion,
+// copies and deterministic Frobenius-norm reductions.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "spin_kernels.hpp"
+
+namespace spin {
+namespace {
+
+constexpr int kNormBlocks = 1024;
+
+__global__ void k_status_reset(int *status, int n) {
+    if ((int)threadIdx.x < n) status[threadIdx.x] = INT_MAX;
+}
+
+// 2-D grid-stride conversion of an (m x n) column-major view.
+template <typename S, typename D>
+__global__ void __launch_bounds__(256)
+    k_convert(const S *__restrict__ src, int64_t lds, D *__restrict__ dst, int64_t ldd, int64_t m,
+              int64_t n) {
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m;
+             i += (int64_t)gridDim.x * 256)
+            dst[i + j * ldd] = (D)src[i + j * lds];
+}
+
+// Per-block partial sums of squares over whole columns (fixed assignment of
+// columns to blocks and fixed in-block order: the result does not depend on
+// scheduling).
+__global__ void __launch_bounds__(256)
+    k_frob_partial(const double *__restrict__ src, int64_t ld, int64_t m, int64_t n,
+                   double *__restrict__ partials) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t j = blockIdx.x; j < n; j += gridDim.x)
+        for (int64_t i = threadIdx.x; i < m; i += 256) {
+            const double v = src[i + j * ld];
+            s = fma(v, v, s);
+        }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_frob_final(const double *__restrict__ partials, int np,
+                                                      double *__restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) s += partials[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// Refinement monitor: flags divergence when |R_j|_F did not decrease.
+__global__ void k_ns_check(const double *norms, int j, int *status) {
+    if (threadIdx.x == 0 && j > 0 && !(norms[j] < norms[j - 1])) status[0] = kStatusNsDiverged;
+}
+
+template <typename S, typename D>
+hipError_t convert(const S *src, int64_t lds, D *dst, int64_t ldd, int64_t m, int64_t n,
+                   hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int64_t bx = (m + 255) / 256;
+    dim3 grid((unsigned)(bx < 64 ? bx : 64), (unsigned)(n < 4096 ? n : 4096));
+    hipLaunchKernelGGL((k_convert<S, D>), grid, dim3(256), 0, s, src, lds, dst, ldd, m, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t status_reset(int *status, int n_words, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, s, status, n_words);
+    return hipGetLastError();
+}
+
+hipError_t cast_f64_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t m,
+                           int64_t n, hipStream_t s) {
+    return convert<double, float>(src, lds, dst, ldd, m, n, s);
+}
+
+hipError_t cast_f32_to_f64(const float *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
+                           int64_t n, hipStream_t s) {
+    return convert<float, double>(src, lds, dst, ldd, m, n, s);
+}
+
+hipError_t copy_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
+                    int64_t n, hipStream_t s) {
+    return convert<double, double>(src, lds, dst, ldd, m, n, s);
+}
+
+hipError_t ns_check(const double *norms, int j, int *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(64), 0, s, norms, j, status);
+    return hipGetLastError();
+}
+
+int frob_partials_count(int64_t m, int64_t n) {
+    (void)m;
+    return (int)(n < kNormBlocks ? (n > 0 ? n : 1) : kNormBlocks);
+}
+
+hipError_t frob2(const double *src, int64_t ld, int64_t m, int64_t n, double *partials,
+                 double *out, hipStream_t s) {
+    const int np = frob_partials_count(m, n);
+    hipLaunchKernelGGL(k_frob_partial, dim3(np), dim3(256), 0, s, src, ld, m, n, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_frob_final, dim3(1), dim3(256), 0, s, partials, np, out);
+    return hipGetLastError();
+}
+
+}  // namespace spin

@@ -1,0 +1,703 @@
+// Host side of the library: recursion planner, executor, per-stream
+// workspace, graph cache, tracing and the exported C ABI (include/spin.h).
+//
+// The planner turns Strassen's inversion scheme (Alg. 1, Sec. 3.1; recursive
+// form Alg. 2, Sec. 3.3) into a flat depth-first list of steps.  The paper's
+// primitives map as follows:
+//   breakMat / xy / arrange (Algs. 3, 4, 6) -> pointer offsets into
+//       column-major storage (no data movement);
+//   multiply + subtract + scalarMul (Alg. 2, Alg. 5) -> block products with a
+//       fused epilogue, S-form: the Schur complement S = A22 - A21 A11^-1 A12
+//       (= -V) is formed directly and inverted into C22, so C22 = S^-1 = -VI,
+//       C12 = -III C22 = III VI and C21 = -C22 II = VI II;
+//   locInverse (Alg. 2, leaf case) -> the leaf Gauss-Jordan kernels.
+// Every internal node issues four launches: {II, III} grouped, S, {C12, C21}
+// grouped, and C11 = C11 - III C21 in place.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "spin.h"
+#include "spin_kernels.hpp"
+
+namespace spin {
+namespace {
+
+// ------------------------------------------------------------------ plan ----
+enum Buf { BUF_A = 0, BUF_X = 1, BUF_WS = 2 };
+
+struct Ref {
+    int buf;
+    int64_t off;
+    int64_t ld;
+};
+
+struct PGemm {
+    Ref a, b, c, d;
+    int64_t m, n, k;
+    double alpha, beta;
+    int add_identity;
+};
+
+struct POp {
+    int kind;  // 0 = products, 1 = leaf
+    int count;
+    int level;
+    PGemm g[2];
+    Ref in, out;
+    int64_t L, col0;
+};
+
+struct Plan {
+    int64_t n = 0, lda = 0, ldx = 0, leaf = 0;
+    std::vector<POp> ops;
+    int64_t ws_elems = 0;
+    int64_t max_leaf = 0;
+    double flops = 0;
+};
+
+// Order of the leading block when an order-m block is split: exact halving
+// for m = leaf * 2^k, otherwise the half rounded up to a multiple of 64 so
+// that block products stay aligned with the 64-wide tiles.
+int64_t split_order(int64_t m) { return m >= 128 ? 64 * ((m + 127) / 128) : (m + 1) / 2; }
+
+Ref sub(const Ref &r, int64_t i, int64_t j) { return Ref{r.buf, r.off + i + j * r.ld, r.ld}; }
+
+void push_products(Plan &P, int level, const PGemm &g0, const PGemm *g1) {
+    POp op{};
+    op.kind = 0;
+    op.level = level;
+    op.g[0] = g0;
+    op.count = 1;
+    if (g1) {
+        op.g[1] = *g1;
+        op.count = 2;
+    }
+    for (int q = 0; q < op.count; ++q) P.flops += 2.0 * op.g[q].m * op.g[q].n * op.g[q].k;
+    P.ops.push_back(op);
+}
+
+void plan_node(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level, int64_t col0) {
+    if (m <= P.leaf) {
+        POp op{};
+        op.kind = 1;
+        op.count = 1;
+        op.level = level;
+        op.in = in;
+        op.out = out;
+        op.L = m;
+        op.col0 = col0;
+        P.ops.push_back(op);
+        P.max_leaf = std::max(P.max_leaf, m);
+        P.flops += 2.0 * m * m * m;
+        return;
+    }
+    const int64_t n1 = split_order(m), n2 = m - n1;
+    const Ref A11 = sub(in, 0, 0), A21 = sub(in, n1, 0), A12 = sub(in, 0, n1),
+              A22 = sub(in, n1, n1);
+    const Ref C11 = sub(out, 0, 0), C21 = sub(out, n1, 0), C12 = sub(out, 0, n1),
+              C22 = sub(out, n1, n1);
+    // I = A11^-1, stored in the C11 view
+    plan_node(P, A11, C11, n1, wsoff, level + 1, col0);
+    // II (n2 x n1), III (n1 x n2) and S (n2 x n2) live until C11 is final
+    const Ref II{BUF_WS, wsoff, n2};
+    const Ref III{BUF_WS, wsoff + n2 * n1, n1};
+    const Ref S{BUF_WS, wsoff + 2 * n1 * n2, n2};
+    const int64_t next = wsoff + 2 * n1 * n2 + n2 * n2;
+    P.ws_elems = std::max(P.ws_elems, next);
+    const Ref none{BUF_WS, 0, 1};
+    // II = A21 I, III = I A12                                   (one launch)
+    const PGemm g_ii{A21, C11, none, II, n2, n1, n1, 1.0, 0.0, 0};
+    const PGemm g_iii{C11, A12, none, III, n1, n2, n1, 1.0, 0.0, 0};
+    push_products(P, level, g_ii, &g_iii);
+    // S = A22 - A21 III  (= -V)
+    push_products(P, level, PGemm{A21, III, A22, S, n2, n2, n1, -1.0, 1.0, 0}, nullptr);
+    // C22 = S^-1  (= -VI)
+    plan_node(P, S, C22, n2, next, level + 1, col0 + n1);
+    // C12 = -III C22 (= III VI), C21 = -C22 II (= VI II)       (one launch)
+    const PGemm g_c12{III, C22, none, C12, n1, n2, n2, -1.0, 0.0, 0};
+    const PGemm g_c21{C22, II, none, C21, n2, n1, n2, -1.0, 0.0, 0};
+    push_products(P, level, g_c12, &g_c21);
+    // C11 = I - III C21, in place on the C11 view
+    push_products(P, level, PGemm{III, C21, C11, C11, n1, n1, n2, -1.0, 1.0, 0}, nullptr);
+}
+
+Plan make_plan(int64_t n, int64_t lda, int64_t ldx, int64_t leaf) {
+    Plan P;
+    P.n = n;
+    P.lda = lda;
+    P.ldx = ldx;
+    P.leaf = leaf;
+    plan_node(P, Ref{BUF_A, 0, lda}, Ref{BUF_X, 0, ldx}, n, 0, 0, 0);
+    return P;
+}
+
+// ------------------------------------------------------------- tracing ----
+struct TraceRec {
+    std::string name;
+    double flops, bytes;
+    int level;
+    hipEvent_t start, stop;
+};
+
+std::mutex g_mu;
+bool g_trace_on = false;
+std::vector<TraceRec> g_trace;
+
+struct TraceCtx {
+    hipStream_t s;
+    int level;
+    hipEvent_t pending;
+};
+
+void trace_cb(void *vctx, const LaunchInfo &li, int phase) {
+    TraceCtx *ctx = static_cast<TraceCtx *>(vctx);
+    if (phase == 0) {
+        hipEventCreate(&ctx->pending);
+        hipEventRecord(ctx->pending, ctx->s);
+    } else {
+        hipEvent_t stop;
+        hipEventCreate(&stop);
+        hipEventRecord(stop, ctx->s);
+        g_trace.push_back(TraceRec{li.name ? li.name : "?", li.flops, li.bytes, ctx->level,
+                                   ctx->pending, stop});
+        ctx->pending = nullptr;
+    }
+}
+
+// ------------------------------------------------------------ workspace ----
+// Layout of a stream's workspace (bytes):
+//   [0, 256)          status words (int): 0 = pivot status, 1 = refinement status
+//   [256, 4096)       small doubles: 0..7 refinement norms, 8..15 misc norms
+//   [4096, +8 KiB)    Frobenius-norm partials
+//   then              recursion workspace, leaf scratch, mixed-mode buffers
+constexpr size_t kHdr = 4096 + 8192 + 4096;
+constexpr int kNormSlots = 8;
+
+inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t rec_off, rec_bytes;
+    size_t leaf_off, leaf_bytes;
+    size_t a32_off, x32_off, r_off, xalt_off;
+    size_t total;
+};
+
+Layout layout_for(int64_t n, int64_t leaf, int mode, int64_t ws_elems, int64_t max_leaf) {
+    Layout L{};
+    const size_t es = (mode == SPIN_FP64) ? 8 : 4;
+    size_t off = kHdr;
+    L.rec_off = off;
+    L.rec_bytes = al256((size_t)ws_elems * es);
+    off += L.rec_bytes;
+    L.leaf_off = off;
+    L.leaf_bytes = al256(leaf_scratch_bytes(max_leaf));
+    off += L.leaf_bytes;
+    if (mode != SPIN_FP64) {
+        const size_t nn = (size_t)n * (size_t)n;
+        L.a32_off = off;
+        off += al256(nn * 4);
+        L.x32_off = off;
+        off += al256(nn * 4);
+        L.r_off = off;
+        off += al256(nn * 8);
+        L.xalt_off = off;
+        off += al256(nn * 8);
+    }
+    (void)leaf;
+    L.total = off;
+    return L;
+}
+
+struct Workspace {
+    char *base = nullptr;
+    size_t bytes = 0;
+};
+
+std::map<hipStream_t, Workspace> g_ws;
+std::map<std::tuple<int, int64_t, int64_t, int64_t, int64_t, const void *, void *, void *, int>,
+         hipGraphExec_t>
+    g_graphs;
+hipStream_t g_capture = nullptr;
+
+void drop_graphs_for(void *base) {
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        if (std::get<7>(it->first) == base) {
+            hipGraphExecDestroy(it->second);
+            it = g_graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// Returns the stream's workspace with at least `bytes` (caller holds g_mu).
+int ws_acquire(hipStream_t s, size_t bytes, Workspace **out) {
+    Workspace &w = g_ws[s];
+    if (w.bytes < bytes) {
+        if (w.base) {
+            hipStreamSynchronize(s);
+            drop_graphs_for(w.base);
+            hipFree(w.base);
+            w.base = nullptr;
+            w.bytes = 0;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return SPIN_E_NOMEM;
+        }
+        w.base = static_cast<char *>(p);
+        w.bytes = bytes;
+    }
+    *out = &w;
+    return SPIN_OK;
+}
+
+// ------------------------------------------------------------- executor ----
+struct Exec {
+    hipStream_t s;
+    char *base[3];
+    size_t es;
+    DType dt;
+    int *status;
+    void *leaf_scratch;
+};
+
+inline void *at(const Exec &E, const Ref &r) {
+    return E.base[r.buf] + (size_t)r.off * E.es;
+}
+
+hipError_t run_plan(const Plan &P, const Exec &E) {
+    for (const POp &op : P.ops) {
+        TraceCtx ctx{E.s, op.level, nullptr};
+        const bool tr = g_trace_on;
+        if (op.kind == 0) {
+            GemmProb pr[2];
+            for (int q = 0; q < op.count; ++q) {
+                const PGemm &g = op.g[q];
+                const bool use_c = g.beta != 0.0;
+                pr[q] = GemmProb{at(E, g.a),       at(E, g.b),  use_c ? at(E, g.c) : nullptr,
+                                 at(E, g.d),       g.a.ld,      g.b.ld,
+                                 use_c ? g.c.ld : 1, g.d.ld,    (int32_t)g.m,
+                                 (int32_t)g.n,     (int32_t)g.k, g.add_identity,
+                                 g.alpha,          g.beta};
+            }
+            LaunchInfo li{};
+            if (tr) trace_cb(&ctx, li, 0);
+            hipError_t e = gemm_launch(pr, op.count, E.dt, E.s, &li);
+            if (tr) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
+        } else {
+            hipError_t e = leaf_launch(at(E, op.in), E.dt, op.in.ld, at(E, op.out), E.dt,
+                                       op.out.ld, op.L, op.col0, E.status, E.leaf_scratch, E.s,
+                                       tr ? trace_cb : nullptr, &ctx);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------- helpers ----
+int validate(const void *A, int64_t n, int64_t lda, const void *X, int64_t ldx, int64_t leaf) {
+    if (!A || !X) return SPIN_E_NULL;
+    if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
+    if (lda < n || ldx < n) return SPIN_E_LD;
+    if (leaf < 1 || leaf > SPIN_MAX_LEAF) return SPIN_E_LEAF;
+    const char *a0 = static_cast<const char *>(A);
+    const char *a1 = a0 + ((size_t)(n - 1) * lda + n) * sizeof(double);
+    const char *x0 = static_cast<const char *>(X);
+    const char *x1 = x0 + ((size_t)(n - 1) * ldx + n) * sizeof(double);
+    if (a0 < x1 && x0 < a1) return SPIN_E_ALIAS;
+    return SPIN_OK;
+}
+
+bool graphs_enabled() {
+    const char *e = std::getenv("SPIN_NO_GRAPH");
+    return !(e && e[0] && e[0] != '0') && !g_trace_on;
+}
+
+int hip_fail(hipError_t e) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? SPIN_E_NOMEM : SPIN_E_HIP;
+}
+
+// Enqueue `body(stream)` either directly or through a cached graph.
+template <typename F>
+int run_maybe_graph(const std::tuple<int, int64_t, int64_t, int64_t, int64_t, const void *, void *,
+                                     void *, int> &key,
+                    hipStream_t s, F body) {
+    if (!graphs_enabled()) {
+        hipError_t e = body(s);
+        return e == hipSuccess ? SPIN_OK : hip_fail(e);
+    }
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        if (!g_capture && hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking) != hipSuccess)
+            return hip_fail(hipErrorUnknown);
+        if (hipStreamBeginCapture(g_capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return hip_fail(hipErrorUnknown);
+        hipError_t e = body(g_capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(g_capture, &graph);
+        if (e != hipSuccess || e2 != hipSuccess || !graph) {
+            if (graph) hipGraphDestroy(graph);
+            return hip_fail(e != hipSuccess ? e : e2);
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e);
+        it = g_graphs.emplace(key, exec).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, s);
+    return e == hipSuccess ? SPIN_OK : hip_fail(e);
+}
+
+int *status_ptr(Workspace *w) { return reinterpret_cast<int *>(w->base); }
+double *norm_ptr(Workspace *w) { return reinterpret_cast<double *>(w->base + 256); }
+double *partials_ptr(Workspace *w) { return reinterpret_cast<double *>(w->base + 4096); }
+
+}  // namespace
+}  // namespace spin
+
+using namespace spin;
+
+extern "C" {
+
+int spin_invert(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx, int64_t leaf,
+                spin_stream_t stream) {
+    int rc = validate(A, n, lda, Ainv, ldx, leaf);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan P = make_plan(n, lda, ldx, leaf);
+    Layout L = layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf);
+    Workspace *w = nullptr;
+    rc = ws_acquire(s, L.total, &w);
+    if (rc) return rc;
+    Exec E{s, {(char *)A, (char *)Ainv, w->base + L.rec_off}, 8, kF64, status_ptr(w),
+           w->base + L.leaf_off};
+    auto body = [&](hipStream_t qs) -> hipError_t {
+        Exec Eq = E;
+        Eq.s = qs;
+        hipError_t e = status_reset(Eq.status, 2, qs);
+        if (e != hipSuccess) return e;
+        return run_plan(P, Eq);
+    };
+    return run_maybe_graph(std::make_tuple(0, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
+                                           (void *)w->base, 0),
+                           s, body);
+}
+
+int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                      int64_t leaf, int mode, int ns_steps, spin_report *rep,
+                      spin_stream_t stream) {
+    int rc = validate(A, n, lda, Ainv, ldx, leaf);
+    if (rc) return rc;
+    if (mode != SPIN_MIXED_FP32 || ns_steps < 0 || ns_steps > kNormSlots) return SPIN_E_MODE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan P = make_plan(n, n, n, leaf);
+    Layout L = layout_for(n, leaf, mode, P.ws_elems, P.max_leaf);
+    Workspace *w = nullptr;
+    rc = ws_acquire(s, L.total, &w);
+    if (rc) return rc;
+    char *base = w->base;
+    float *A32 = reinterpret_cast<float *>(base + L.a32_off);
+    float *X32 = reinterpret_cast<float *>(base + L.x32_off);
+    double *R = reinterpret_cast<double *>(base + L.r_off);
+    double *Xalt = reinterpret_cast<double *>(base + L.xalt_off);
+    int *status = status_ptr(w);
+    double *norms = norm_ptr(w);
+    double *parts = partials_ptr(w);
+    // Buffers alternate between refinement steps so that the last step writes Ainv.
+    double *buf0 = (ns_steps % 2 == 0) ? Ainv : Xalt;
+    const int64_t ld0 = (ns_steps % 2 == 0) ? ldx : n;
+    double *buf1 = (ns_steps % 2 == 0) ? Xalt : Ainv;
+    const int64_t ld1 = (ns_steps % 2 == 0) ? n : ldx;
+
+    auto body = [&](hipStream_t qs) -> hipError_t {
+        hipError_t e = status_reset(status, 2, qs);
+        if (e != hipSuccess) return e;
+        e = cast_f64_to_f32(A, lda, A32, n, n, n, qs);
+        if (e != hipSuccess) return e;
+        Exec E{qs, {(char *)A32, (char *)X32, base + L.rec_off}, 4, kF32, status,
+               base + L.leaf_off};
+        e = run_plan(P, E);
+        if (e != hipSuccess) return e;
+        e = cast_f32_to_f64(X32, n, buf0, ld0, n, n, qs);
+        if (e != hipSuccess) return e;
+        for (int j = 0; j < ns_steps; ++j) {
+            double *xc = (j % 2 == 0) ? buf0 : buf1;
+            const int64_t ldc = (j % 2 == 0) ? ld0 : ld1;
+            double *xn = (j % 2 == 0) ? buf1 : buf0;
+            const int64_t ldn = (j % 2 == 0) ? ld1 : ld0;
+            TraceCtx ctx{qs, -1, nullptr};
+            // R = I - A X
+            GemmProb pr{A, xc, nullptr, R, lda, ldc, 1, n, (int32_t)n, (int32_t)n, (int32_t)n,
+                        1, -1.0, 0.0};
+            LaunchInfo li{};
+            if (g_trace_on) trace_cb(&ctx, li, 0);
+            e = gemm_launch(&pr, 1, kF64, qs, &li);
+            if (g_trace_on) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
+            e = frob2(R, n, n, n, parts, norms + j, qs);
+            if (e != hipSuccess) return e;
+            e = ns_check(norms, j, status + 1, qs);
+            if (e != hipSuccess) return e;
+            // X' = X + X R
+            GemmProb pu{xc, R, xc, xn, ldc, n, ldc, ldn, (int32_t)n, (int32_t)n, (int32_t)n,
+                        0, 1.0, 1.0};
+            if (g_trace_on) trace_cb(&ctx, li, 0);
+            e = gemm_launch(&pu, 1, kF64, qs, &li);
+            if (g_trace_on) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    rc = run_maybe_graph(std::make_tuple(1 + 16 * mode, n, lda, ldx, leaf, (const void *)A,
+                                         (void *)Ainv, (void *)base, ns_steps),
+                         s, body);
+    if (rc || !rep) return rc;
+
+    // Report: residual of the unrefined and of the final inverse.
+    std::memset(rep, 0, sizeof(*rep));
+    rep->steps = ns_steps;
+    double *misc = norms + kNormSlots;  // 0: |A|^2, 1: |X0|^2, 2: |R_final|^2, 3: |X|^2
+    hipError_t e = frob2(A, lda, n, n, parts, misc + 0, s);
+    // X0 is no longer stored once refinement ran: recompute it from X32.
+    double *x0 = (ns_steps > 0) ? R : Ainv;
+    int64_t ldx0 = (ns_steps > 0) ? n : ldx;
+    if (e == hipSuccess && ns_steps > 0) e = cast_f32_to_f64(X32, n, R, n, n, n, s);
+    if (e == hipSuccess) e = frob2(x0, ldx0, n, n, parts, misc + 1, s);
+    if (e == hipSuccess && ns_steps == 0) {
+        GemmProb pr{A, Ainv, nullptr, R, lda, ldx, 1, n, (int32_t)n, (int32_t)n, (int32_t)n,
+                    1, -1.0, 0.0};
+        e = gemm_launch(&pr, 1, kF64, s, nullptr);
+        if (e == hipSuccess) e = frob2(R, n, n, n, parts, norms + 0, s);
+    }
+    // final residual
+    if (e == hipSuccess) {
+        GemmProb pr{A, Ainv, nullptr, R, lda, ldx, 1, n, (int32_t)n, (int32_t)n, (int32_t)n,
+                    1, -1.0, 0.0};
+        e = gemm_launch(&pr, 1, kF64, s, nullptr);
+    }
+    if (e == hipSuccess) e = frob2(R, n, n, n, parts, misc + 2, s);
+    if (e == hipSuccess) e = frob2(Ainv, ldx, n, n, parts, misc + 3, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    double h_norms[kNormSlots + 4];
+    int h_status[2];
+    if (e == hipSuccess) e = hipMemcpy(h_norms, norms, sizeof(h_norms), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(h_status, status, sizeof(h_status), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    const double na = std::sqrt(h_norms[kNormSlots + 0]);
+    const double nx0 = std::sqrt(h_norms[kNormSlots + 1]);
+    const double nr = std::sqrt(h_norms[kNormSlots + 2]);
+    const double nx = std::sqrt(h_norms[kNormSlots + 3]);
+    rep->r0_fro = std::sqrt(h_norms[0]);
+    for (int j = 0; j < ns_steps; ++j) rep->r_fro[j] = std::sqrt(h_norms[j]);
+    rep->rho_before = rep->r0_fro / (na * nx0);
+    rep->rho_after = nr / (na * nx);
+    rep->status = (h_status[0] != INT32_MAX) ? h_status[0]
+                  : (h_status[1] != INT32_MAX) ? h_status[1]
+                                               : 0;
+    return SPIN_OK;
+}
+
+int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
+              int64_t lda, const void *B, int64_t ldb, double beta, const void *C0, int64_t ldc,
+              void *D, int64_t ldd, int add_identity, spin_stream_t stream) {
+    if (dtype != SPIN_FP64 && dtype != SPIN_MIXED_FP32) return SPIN_E_MODE;
+    if (m < 0 || n < 0 || k < 0 || m > INT32_MAX || n > INT32_MAX || k > INT32_MAX)
+        return SPIN_E_N;
+    if (!D || (k > 0 && (!A || !B)) || (beta != 0.0 && !C0)) return SPIN_E_NULL;
+    if (ldd < std::max<int64_t>(m, 1) || (k > 0 && (lda < std::max<int64_t>(m, 1) ||
+                                                    ldb < std::max<int64_t>(k, 1))) ||
+        (beta != 0.0 && ldc < std::max<int64_t>(m, 1)))
+        return SPIN_E_LD;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    GemmProb pr{A, B, beta != 0.0 ? C0 : nullptr, D, lda, ldb, beta != 0.0 ? ldc : 1, ldd,
+                (int32_t)m, (int32_t)n, (int32_t)k, add_identity ? 1 : 0, alpha, beta};
+    std::lock_guard<std::mutex> lk(g_mu);
+    TraceCtx ctx{s, -1, nullptr};
+    LaunchInfo li{};
+    if (g_trace_on) trace_cb(&ctx, li, 0);
+    hipError_t e = gemm_launch(&pr, 1, dtype == SPIN_FP64 ? kF64 : kF32, s, &li);
+    if (g_trace_on) trace_cb(&ctx, li, 1);
+    return e == hipSuccess ? SPIN_OK : hip_fail(e);
+}
+
+int spin_info(spin_stream_t stream) {
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int h[2] = {INT32_MAX, INT32_MAX};
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_ws.find(s);
+        if (it == g_ws.end() || !it->second.base) return SPIN_OK;
+        if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(hipErrorUnknown);
+        if (hipMemcpy(h, it->second.base, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+            return hip_fail(hipErrorUnknown);
+    }
+    if (h[0] != INT32_MAX) return h[0];
+    if (h[1] != INT32_MAX) return h[1];
+    return SPIN_OK;
+}
+
+int spin_residual(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
+                  double *rho, spin_stream_t stream) {
+    if (!A || !X || !rho) return SPIN_E_NULL;
+    if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
+    if (lda < n || ldx < n) return SPIN_E_LD;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *w = nullptr;
+    int rc = ws_acquire(s, kHdr + al256((size_t)n * n * 8), &w);
+    if (rc) return rc;
+    double *R = reinterpret_cast<double *>(w->base + kHdr);
+    double *norms = norm_ptr(w) + kNormSlots + 4;  // 3 slots after the mixed-mode ones
+    double *parts = partials_ptr(w);
+    GemmProb pr{A, X, nullptr, R, lda, ldx, 1, n, (int32_t)n, (int32_t)n, (int32_t)n, 1, -1.0, 0.0};
+    hipError_t e = gemm_launch(&pr, 1, kF64, s, nullptr);
+    if (e == hipSuccess) e = frob2(R, n, n, n, parts, norms + 0, s);
+    if (e == hipSuccess) e = frob2(A, lda, n, n, parts, norms + 1, s);
+    if (e == hipSuccess) e = frob2(X, ldx, n, n, parts, norms + 2, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    double h[3];
+    if (e == hipSuccess) e = hipMemcpy(h, norms, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e);
+    *rho = std::sqrt(h[0]) / (std::sqrt(h[1]) * std::sqrt(h[2]));
+    return SPIN_OK;
+}
+
+size_t spin_workspace_bytes(int64_t n, int64_t leaf, int mode) {
+    if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > SPIN_MAX_LEAF) return 0;
+    if (mode != SPIN_FP64 && mode != SPIN_MIXED_FP32) return 0;
+    Plan P = make_plan(n, n, n, leaf);
+    return layout_for(n, leaf, mode, P.ws_elems, P.max_leaf).total;
+}
+
+const char *spin_strerror(int code) {
+    switch (code) {
+    case SPIN_OK: return "success";
+    case SPIN_E_NULL: return "null pointer argument";
+    case SPIN_E_N: return "matrix order out of range";
+    case SPIN_E_LD: return "leading dimension smaller than the matrix order";
+    case SPIN_E_LEAF: return "leaf order out of range";
+    case SPIN_E_ALIAS: return "input and output overlap";
+    case SPIN_E_MODE: return "unknown precision mode or refinement step count";
+    case SPIN_E_COUNT: return "batch count out of range";
+    case SPIN_E_NOMEM: return "device memory allocation failed";
+    case SPIN_E_HIP: return "HIP runtime or kernel launch error";
+    case SPIN_NS_DIVERGED: return "Newton refinement residual did not decrease";
+    default: return code > 0 ? "zero or non-finite pivot in a leaf block" : "unknown status";
+    }
+}
+
+void spin_release(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    hipDeviceSynchronize();
+    for (auto &kv : g_graphs) hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+    for (auto &kv : g_ws)
+        if (kv.second.base) hipFree(kv.second.base);
+    g_ws.clear();
+}
+
+int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf, spin_plan_op *ops,
+                           int64_t cap, double *flops) {
+    if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
+    if (lda < n || ldx < n) return SPIN_E_LD;
+    if (leaf < 1 || leaf > SPIN_MAX_LEAF) return SPIN_E_LEAF;
+    if (cap > 0 && !ops) return SPIN_E_NULL;
+    Plan P = make_plan(n, lda, ldx, leaf);
+    if (flops) *flops = P.flops;
+    const int64_t cnt = (int64_t)P.ops.size();
+    for (int64_t i = 0; i < cnt && i < cap; ++i) {
+        const POp &op = P.ops[(size_t)i];
+        spin_plan_op o;
+        std::memset(&o, 0, sizeof(o));
+        o.kind = op.kind;
+        o.count = op.count;
+        o.level = op.level;
+        if (op.kind == 0) {
+            for (int q = 0; q < op.count; ++q) {
+                const PGemm &g = op.g[q];
+                o.m[q] = g.m;
+                o.n[q] = g.n;
+                o.k[q] = g.k;
+                o.a_buf[q] = g.a.buf;
+                o.b_buf[q] = g.b.buf;
+                o.c_buf[q] = g.beta != 0.0 ? g.c.buf : -1;
+                o.d_buf[q] = g.d.buf;
+                o.a_off[q] = g.a.off;
+                o.b_off[q] = g.b.off;
+                o.c_off[q] = g.c.off;
+                o.d_off[q] = g.d.off;
+                o.a_ld[q] = g.a.ld;
+                o.b_ld[q] = g.b.ld;
+                o.c_ld[q] = g.c.ld;
+                o.d_ld[q] = g.d.ld;
+                o.alpha[q] = g.alpha;
+                o.beta[q] = g.beta;
+            }
+        } else {
+            o.a_buf[0] = op.in.buf;
+            o.a_off[0] = op.in.off;
+            o.a_ld[0] = op.in.ld;
+            o.d_buf[0] = op.out.buf;
+            o.d_off[0] = op.out.off;
+            o.d_ld[0] = op.out.ld;
+            o.leaf_order = op.L;
+            o.col0 = op.col0;
+        }
+        ops[i] = o;
+    }
+    return cnt;
+}
+
+int64_t spin_plan_ws_elems(int64_t n, int64_t leaf) {
+    if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > SPIN_MAX_LEAF) return SPIN_E_N;
+    return make_plan(n, n, n, leaf).ws_elems;
+}
+
+int spin_trace_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_trace_on = on != 0;
+    return SPIN_OK;
+}
+
+int64_t spin_trace_collect(spin_trace_rec *recs, int64_t cap) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const int64_t cnt = (int64_t)g_trace.size();
+    for (int64_t i = 0; i < cnt; ++i) {
+        TraceRec &t = g_trace[(size_t)i];
+        float ms = 0.f;
+        hipEventSynchronize(t.stop);
+        hipEventElapsedTime(&ms, t.start, t.stop);
+        if (recs && i < cap) {
+            spin_trace_rec &r = recs[i];
+            std::memset(&r, 0, sizeof(r));
+            std::snprintf(r.kernel, sizeof(r.kernel), "%s", t.name.c_str());
+            r.ms = ms;
+            r.flops = t.flops;
+            r.bytes = t.bytes;
+            r.level = t.level;
+        }
+        hipEventDestroy(t.start);
+        hipEventDestroy(t.stop);
+    }
+    g_trace.clear();
+    return cnt;
+}
+
+}  // extern "C"

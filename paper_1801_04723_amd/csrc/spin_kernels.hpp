@@ -1,0 +1,74 @@
+// Internal interface between the host scheduler (spin_api.cpp) and the HIP
+// kernels (gemm.hip, leaf.hip, aux.hip).  Not installed; the public ABI is
+// include/spin.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spin {
+
+enum DType : int32_t { kF64 = 0, kF32 = 1 };
+
+// Largest leaf order the leaf kernels accept.
+constexpr int kLeafMaxOrder = 2048;
+
+// One block product  D = alpha * A * B + beta * C0 (+ I),  column-major views.
+struct GemmProb {
+    const void *A;
+    const void *B;
+    const void *C0;
+    void *D;
+    int64_t lda, ldb, ldc, ldd;
+    int32_t m, n, k;
+    int32_t add_identity;
+    double alpha, beta;
+};
+
+// A launch of up to kMaxGroup independent products (one grid; every
+// workgroup finds its problem from the tile prefix sums).
+constexpr int kMaxGroup = 4;
+
+// Per-launch bookkeeping returned to the scheduler for tracing.
+struct LaunchInfo {
+    const char *name;  // kernel family + tile shape (static string)
+    double flops;
+    double bytes;
+};
+
+// GEMM family (gemm.hip).  dt selects operand/result type and MFMA flavour.
+hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s,
+                       LaunchInfo *info);
+
+// Leaf inversion, Gauss-Jordan with partial pivoting in FP64 (leaf.hip).
+//   in  : order-L block, element type `in_dt`, leading dimension ldi
+//   out : order-L block, element type `out_dt`, leading dimension ldo
+//   status : device int, atomically lowered to col0 + k + 1 on a failing pivot
+//   scratch: FP64 scratch for the blocked tier (leaf_scratch_bytes(L) bytes)
+size_t leaf_scratch_bytes(int64_t L);
+// Number of kernel launches leaf_launch() issues for order L (tracing aid).
+hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DType out_dt,
+                       int64_t ldo, int64_t L, int64_t col0, int *status, void *scratch,
+                       hipStream_t s, void (*trace_cb)(void *, const LaunchInfo &, int),
+                       void *trace_ctx);
+
+// Auxiliary kernels (aux.hip).
+// Status words start at INT_MAX ("no event"); kernels lower them atomically.
+hipError_t status_reset(int *status, int n_words, hipStream_t s);
+// Value written to the refinement status word on divergence (SPIN_NS_DIVERGED).
+constexpr int kStatusNsDiverged = -100;
+hipError_t ns_check(const double *norms, int j, int *status, hipStream_t s);
+hipError_t cast_f64_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t m,
+                           int64_t n, hipStream_t s);
+hipError_t cast_f32_to_f64(const float *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
+                           int64_t n, hipStream_t s);
+hipError_t copy_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
+                    int64_t n, hipStream_t s);
+// Sum of squares of an (m x n) FP64 view, deterministic two-pass reduction:
+// partials (>= frob_partials_count(m, n) doubles) then one block writes *out.
+int frob_partials_count(int64_t m, int64_t n);
+hipError_t frob2(const double *src, int64_t ld, int64_t m, int64_t n, double *partials,
+                 double *out, hipStream_t s);
+
+}  // namespace spin

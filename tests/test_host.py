@@ -1,0 +1,156 @@
+"""Host-side tests of the GPU library (no GPU needed).
+
+* the shared library loads and exports every function include/spin.h declares;
+* argument validation returns the documented codes before touching the GPU;
+* the recursion schedule has the structure Alg. 2 prescribes (counts per
+  internal node, leaves, levels), the flop count 2 n^3, the n^2 - L^2
+  workspace bound, and the same split rule as the oracle;
+* replaying the library's schedule on the CPU with the oracle's product and
+  leaf inverse reproduces the oracle's literal Strassen recursion bit for bit
+  (S-form schedule == V-form algorithm under IEEE sign symmetry).
+"""
+import ctypes
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1801_04723_amd as S
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_library_exports_every_header_symbol():
+    L = S.lib()
+    names = S.header_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_strerror_covers_codes():
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -10, -11, -100, 17):
+        assert S.strerror(code)
+    assert "overlap" in S.strerror(-5)
+
+
+def test_argument_validation_codes():
+    L = S.lib()
+    p = ctypes.c_void_p
+    A = p(0x10000000)
+    X = p(0x20000000)
+    s = p(0)
+    assert L.spin_invert(None, 4, 4, X, 4, 2, s) == -1
+    assert L.spin_invert(A, 0, 4, X, 4, 2, s) == -2
+    assert L.spin_invert(A, 8, 4, X, 8, 2, s) == -3
+    assert L.spin_invert(A, 8, 8, X, 7, 2, s) == -3
+    assert L.spin_invert(A, 8, 8, X, 8, 0, s) == -4
+    assert L.spin_invert(A, 8, 8, X, 8, 4096, s) == -4
+    # overlapping ranges: X starts inside A's last column
+    assert L.spin_invert(A, 8, 8, p(0x10000000 + 8 * 60), 8, 2, s) == -5
+    assert L.spin_invert_mixed(A, 8, 8, X, 8, 2, 7, 2, None, s) == -6
+    assert L.spin_invert_mixed(A, 8, 8, X, 8, 2, 1, 9, None, s) == -6
+    assert L.spin_gemm(5, 4, 4, 4, 1.0, A, 4, A, 4, 0.0, None, 4, X, 4, 0, s) == -6
+    assert L.spin_gemm(0, 4, 4, 4, 1.0, A, 3, A, 4, 0.0, None, 4, X, 4, 0, s) == -3
+    assert L.spin_gemm(0, 4, 4, 4, 1.0, A, 4, A, 4, 1.0, None, 4, X, 4, 0, s) == -1
+    assert L.spin_workspace_bytes(0, 4, 0) == 0
+    assert L.spin_workspace_bytes(64, 4, 9) == 0
+
+
+def _levels(n, leaf):
+    return 0 if n <= leaf else 1 + max(_levels(oracle.split(n), leaf), _levels(n - oracle.split(n), leaf))
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (8192, 256), (16384, 128), (16384, 2048), (2048, 2048)])
+def test_schedule_counts_and_flops(n, leaf):
+    ops, fl = S.plan_describe(n, leaf)
+    d = int(math.log2(n // leaf))
+    counts = json.load(open(os.path.join(GOLDEN, "paper_counts.json")))
+    leaves = [o for o in ops if o["kind"] == "leaf"]
+    prods = [o for o in ops if o["kind"] == "products"]
+    internal = 2 ** d - 1
+    assert len(leaves) == 2 ** d                          # 2^(p-q) leaves
+    assert len(prods) == 4 * internal                     # launches per node
+    logical = sum(len(o["products"]) for o in prods)
+    assert logical == counts["multiply_per_internal_node"] * internal
+    # the two `subtract`s of each node become beta = 1 epilogues
+    subtracts = sum(1 for o in prods for p in o["products"] if p["beta"] == 1.0)
+    assert subtracts == counts["subtract_per_internal_node"] * internal
+    assert fl == 2.0 * n ** 3
+    # 2^i nodes at level i (Fig. 1)
+    for lvl in range(d):
+        nodes = {o["products"][0]["d"] for o in prods if o["level"] == lvl}
+        assert len([o for o in prods if o["level"] == lvl]) == 4 * 2 ** lvl
+    assert all(o["L"] == leaf for o in leaves)
+    assert max(o["level"] for o in leaves) == d
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (1024, 128), (8192, 256), (300, 64), (4160, 128), (100, 7)])
+def test_workspace_bound(n, leaf):
+    ws = S.plan_ws_elems(n, leaf)
+    assert ws <= n * n
+    if n % leaf == 0 and (n // leaf) & (n // leaf - 1) == 0:
+        assert ws == n * n - leaf * leaf
+    assert S.workspace_bytes(n, leaf, "fp64") >= 8 * ws
+    assert S.workspace_bytes(n, leaf, "fp32") >= 4 * ws + 24 * n * n
+
+
+@pytest.mark.parametrize("m", list(range(1, 300, 7)) + [4096, 4160, 8191, 16384])
+def test_split_rule_matches_oracle(m):
+    if m == 1:
+        ops, _ = S.plan_describe(1, 1)
+        assert len(ops) == 1 and ops[0]["kind"] == "leaf"
+        return
+    ops, _ = S.plan_describe(m, min(m - 1, 2048))
+    top = next(o for o in ops if o["kind"] == "products" and o["level"] == 0)
+    n1 = top["products"][0]["k"]  # II = A21 I has inner dimension n1
+    assert n1 == oracle.split(m)
+
+
+def _run_schedule_on_cpu(A, leaf):
+    """Replay the library's schedule with the oracle's GEMM and GJ."""
+    n = A.shape[0]
+    ops, _ = S.plan_describe(n, leaf)
+    bufs = [np.asfortranarray(A).ravel(order="F").copy(),
+            np.zeros(n * n), np.zeros(max(S.plan_ws_elems(n, leaf), 1))]
+
+    def view(ref, r, c):
+        b, off, ld = ref
+        flat = bufs[b]
+        return np.lib.stride_tricks.as_strided(flat[off:], shape=(r, c), strides=(8, 8 * ld))
+
+    for o in ops:
+        if o["kind"] == "leaf":
+            L = o["L"]
+            src = np.array(view(o["src"], L, L))
+            x, info = oracle.gj_inv(src)
+            assert info == 0
+            dst = view(o["dst"], L, L)
+            dst[...] = x
+        else:
+            results = []
+            for p in o["products"]:
+                a = np.array(view(p["a"], p["m"], p["k"]))
+                b = np.array(view(p["b"], p["k"], p["n"]))
+                prod = oracle.gemm(a, b)
+                d = p["alpha"] * prod
+                if p["beta"] != 0.0:
+                    d = d + p["beta"] * np.array(view(p["c"], p["m"], p["n"]))
+                results.append((p, d))
+            for p, d in results:
+                view(p["d"], p["m"], p["n"])[...] = d
+    return bufs[1].reshape((n, n), order="F")
+
+
+@pytest.mark.parametrize("gen,n,leaf", [("dd", 256, 64), ("spd", 128, 16), ("dd", 200, 32), ("hh", 96, 16)])
+def test_schedule_replay_equals_oracle_bitwise(gen, n, leaf):
+    A = {"dd": lambda: W.diag_dominant(n, 1), "spd": lambda: W.spd_gram(n, 2),
+         "hh": lambda: W.householder(n, 3)}[gen]()
+    X = _run_schedule_on_cpu(A, leaf)
+    ref, info = oracle.strassen_inv(A, leaf)
+    assert info == 0
+    assert np.array_equal(X, ref)
