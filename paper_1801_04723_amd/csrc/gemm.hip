@@ -201,6 +201,173 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs g) {
     }
 }
 
+// Fast path.  Requires 16-byte aligned operands, leading dimensions that are
+// multiples of the vector width, M a multiple of the vector width and K a
+// multiple of BK -- true for every block product of the recursion when the
+// order is a multiple of 64.  The main loop then has no control flow: the
+// edge rows/columns of a tile are clamped once and masked, each thread keeps
+// one pointer per 16-byte global load and advances it by one slab per step.
+//
+// The K slab is split into four contiguous chunks of KQ = BK/4 values, one per
+// lane group q = lane/16, and MFMA step kk consumes k = q*KQ + kk in group q
+// (any assignment of k to the four MFMA k-slots is valid as long as A and B
+// agree).  B is staged k-contiguous (Bs[n][k]) so that a lane fetches its KQ
+// B values with 16-byte LDS reads; A is staged m-contiguous (As[k][m]).
+template <int BM, int BN, int BK, int WM, int WN, typename T>
+__global__ void __launch_bounds__(256) gemm_fast(GroupArgs g) {
+    constexpr int NT = 256;
+    constexpr int VW = 16 / sizeof(T);
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    constexpr int WAVES_M = BM / WM;
+    static_assert(WAVES_M * (BN / WN) == 4, "four waves per workgroup");
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int KQ = BK / 4;
+    static_assert(KQ % VW == 0, "lane chunk must be whole vectors");
+    constexpr int A_LD = BM + VW;  // As[k][m]
+    constexpr int B_LD = BK + VW;  // Bs[n][k]
+    constexpr int AV = BM * BK / VW / NT;
+    constexpr int BV = BN * BK / VW / NT;
+    static_assert(AV * VW * NT == BM * BK && BV * VW * NT == BN * BK, "tile/thread mismatch");
+    using acc_t = typename Mma<T>::acc_t;
+
+    __shared__ __attribute__((aligned(16))) T As[2][BK * A_LD];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BN * B_LD];
+
+    const int bid = blockIdx.x;
+    int pi = 0;
+#pragma unroll
+    for (int q = 1; q < kMaxGroup; ++q)
+        if (q < g.count && bid >= g.tile_start[q]) pi = q;
+    GemmProb P = g.p[0];
+    int tstart = g.tile_start[0], tiles_m = g.tiles_m[0];
+#pragma unroll
+    for (int q = 1; q < kMaxGroup; ++q)
+        if (pi == q) {
+            P = g.p[q];
+            tstart = g.tile_start[q];
+            tiles_m = g.tiles_m[q];
+        }
+    const int t = bid - tstart;
+    const int tm = t % tiles_m, tn = t / tiles_m;
+    const int M = P.m, N = P.n, K = P.k;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int64_t lda = P.lda, ldb = P.ldb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % WAVES_M) * WM, wn0 = (wave / WAVES_M) * WN;
+
+    const T *pa[AV];
+    bool am[AV];
+    int sa[AV];
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+        const int v = tid + NT * i, r = (v % (BM / VW)) * VW, c = v / (BM / VW);
+        am[i] = m0 + r < M;
+        const int row = am[i] ? m0 + r : M - VW;
+        pa[i] = static_cast<const T *>(P.A) + row + (int64_t)c * lda;
+        sa[i] = c * A_LD + r;
+    }
+    const T *pb[BV];
+    bool bm[BV];
+    int sb[BV];
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+        const int v = tid + NT * i, k = (v % (BK / VW)) * VW, n = v / (BK / VW);
+        bm[i] = n0 + n < N;
+        const int col = bm[i] ? n0 + n : N - 1;
+        pb[i] = static_cast<const T *>(P.B) + k + (int64_t)col * ldb;
+        sb[i] = n * B_LD + k;
+    }
+    const int64_t astep = (int64_t)BK * lda;
+
+    vec_t ra[AV], rb[BV];
+    auto gload = [&]() {
+#pragma unroll
+        for (int i = 0; i < AV; ++i) {
+            const vec_t x = *reinterpret_cast<const vec_t *>(pa[i]);
+            ra[i] = am[i] ? x : vec_t(0);
+            pa[i] += astep;
+        }
+#pragma unroll
+        for (int i = 0; i < BV; ++i) {
+            const vec_t x = *reinterpret_cast<const vec_t *>(pb[i]);
+            rb[i] = bm[i] ? x : vec_t(0);
+            pb[i] += BK;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < AV; ++i) *reinterpret_cast<vec_t *>(&As[buf][sa[i]]) = ra[i];
+#pragma unroll
+        for (int i = 0; i < BV; ++i) *reinterpret_cast<vec_t *>(&Bs[buf][sb[i]]) = rb[i];
+    };
+
+    acc_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    const int q = lane >> 4, c16 = lane & 15;
+    auto compute = [&](int buf) {
+        const T *as = &As[buf][(q * KQ) * A_LD + wm0 + c16];
+        const T *bs = &Bs[buf][(wn0 + c16) * B_LD + q * KQ];
+        vec_t bv[TN][KQ / VW];
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int h = 0; h < KQ / VW; ++h)
+                bv[j][h] = *reinterpret_cast<const vec_t *>(bs + j * 16 * B_LD + h * VW);
+#pragma unroll
+        for (int kk = 0; kk < KQ; ++kk) {
+            T a[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = as[kk * A_LD + i * 16];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = Mma<T>::mma(bv[j][kk / VW][kk % VW], a[i], acc[i][j]);
+        }
+    };
+
+    const int KT = K / BK;
+    if (KT > 0) {
+        gload();
+        sstore(0);
+        __syncthreads();
+        for (int kt = 0; kt + 1 < KT; ++kt) {
+            gload();
+            compute(kt & 1);
+            sstore((kt & 1) ^ 1);
+            __syncthreads();
+        }
+        compute((KT - 1) & 1);
+    }
+
+    const T *__restrict__ C0 = static_cast<const T *>(P.C0);
+    T *D = static_cast<T *>(P.D);
+    const double alpha = P.alpha, beta = P.beta;
+    const bool use_c = (beta != 0.0) && (C0 != nullptr);
+    const bool add_i = P.add_identity != 0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int gm = m0 + wm0 + i * 16 + c16;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gn = n0 + wn0 + j * 16 + Mma<T>::ncol(lane, v);
+                if (gm < M && gn < N) {
+                    double val = alpha * (double)acc[i][j][v];
+                    if (use_c) val += beta * (double)C0[gm + (int64_t)gn * P.ldc];
+                    if (add_i && gm == gn) val += 1.0;
+                    D[gm + (int64_t)gn * P.ldd] = (T)val;
+                }
+            }
+        }
+    }
+}
+
 template <int BM, int BN, int BK, int WM, int WN, typename T>
 hipError_t launch_cfg(const GemmProb *probs, int count, hipStream_t s) {
     GroupArgs g{};
@@ -232,6 +399,44 @@ int64_t tiles_for(const GemmProb *probs, int count, int bm, int bn) {
     return t;
 }
 
+
+constexpr int kFastBK128 = 16;
+
+// Conditions of the fast path for every product of a launch.
+bool fast_ok(const GemmProb *probs, int count, int vw, int bk) {
+    for (int q = 0; q < count; ++q) {
+        const GemmProb &p = probs[q];
+        if (p.k <= 0 || p.k % bk != 0 || p.m % vw != 0) return false;
+        if (p.lda % vw != 0 || p.ldb % vw != 0) return false;
+        if ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.B)) & 15) return false;
+    }
+    return true;
+}
+
+template <int BM, int BN, int BK, int WM, int WN, typename T>
+hipError_t launch_fast(const GemmProb *probs, int count, hipStream_t s) {
+    GroupArgs g{};
+    g.count = count;
+    int total = 0;
+    for (int q = 0; q < kMaxGroup; ++q) {
+        if (q < count) {
+            g.p[q] = probs[q];
+            const int tm = (probs[q].m + BM - 1) / BM, tn = (probs[q].n + BN - 1) / BN;
+            g.tile_start[q] = total;
+            g.tiles_m[q] = tm > 0 ? tm : 1;
+            total += tm * tn;
+        } else {
+            g.p[q] = probs[0];
+            g.tile_start[q] = 1 << 30;
+            g.tiles_m[q] = 1;
+        }
+    }
+    g.tile_start[kMaxGroup] = total;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T>), dim3(total), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s, LaunchInfo *info) {
@@ -253,31 +458,40 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
     // fall back to smaller tiles so that more workgroups run concurrently.
     const int64_t t128 = tiles_for(live, n_live, 128, 128);
     const int64_t t64 = tiles_for(live, n_live, 64, 64);
-    const char *name;
+    const int tile = (t128 >= 256) ? 128 : (t64 >= 256) ? 64 : 32;
+    const int bk = (tile == 128) ? kFastBK128 : 32;
+    const bool fast = n_live > 0 && fast_ok(live, n_live, dt == kF64 ? 2 : 4, bk);
+    const char *name = "gemm_empty";
     hipError_t e = hipSuccess;
-    if (n_live == 0) {
-        name = "gemm_empty";
-    } else if (dt == kF64) {
-        if (t128 >= 256) {
-            name = "gemm_f64_128x128";
-            e = launch_cfg<128, 128, 16, 64, 64, double>(live, n_live, s);
-        } else if (t64 >= 256) {
-            name = "gemm_f64_64x64";
-            e = launch_cfg<64, 64, 16, 32, 32, double>(live, n_live, s);
+    if (n_live > 0) {
+        if (dt == kF64) {
+            if (tile == 128) {
+                name = fast ? "gemm_f64_128x128" : "gemm_f64_128x128_edge";
+                e = fast ? launch_fast<128, 128, kFastBK128, 64, 64, double>(live, n_live, s)
+                         : launch_cfg<128, 128, 16, 64, 64, double>(live, n_live, s);
+            } else if (tile == 64) {
+                name = fast ? "gemm_f64_64x64" : "gemm_f64_64x64_edge";
+                e = fast ? launch_fast<64, 64, 32, 32, 32, double>(live, n_live, s)
+                         : launch_cfg<64, 64, 16, 32, 32, double>(live, n_live, s);
+            } else {
+                name = fast ? "gemm_f64_32x32" : "gemm_f64_32x32_edge";
+                e = fast ? launch_fast<32, 32, 32, 16, 16, double>(live, n_live, s)
+                         : launch_cfg<32, 32, 32, 16, 16, double>(live, n_live, s);
+            }
         } else {
-            name = "gemm_f64_32x32";
-            e = launch_cfg<32, 32, 32, 16, 16, double>(live, n_live, s);
-        }
-    } else {
-        if (t128 >= 256) {
-            name = "gemm_f32_128x128";
-            e = launch_cfg<128, 128, 16, 64, 64, float>(live, n_live, s);
-        } else if (t64 >= 256) {
-            name = "gemm_f32_64x64";
-            e = launch_cfg<64, 64, 16, 32, 32, float>(live, n_live, s);
-        } else {
-            name = "gemm_f32_32x32";
-            e = launch_cfg<32, 32, 32, 16, 16, float>(live, n_live, s);
+            if (tile == 128) {
+                name = fast ? "gemm_f32_128x128" : "gemm_f32_128x128_edge";
+                e = fast ? launch_fast<128, 128, 32, 64, 64, float>(live, n_live, s)
+                         : launch_cfg<128, 128, 16, 64, 64, float>(live, n_live, s);
+            } else if (tile == 64) {
+                name = fast ? "gemm_f32_64x64" : "gemm_f32_64x64_edge";
+                e = fast ? launch_fast<64, 64, 32, 32, 32, float>(live, n_live, s)
+                         : launch_cfg<64, 64, 16, 32, 32, float>(live, n_live, s);
+            } else {
+                name = fast ? "gemm_f32_32x32" : "gemm_f32_32x32_edge";
+                e = fast ? launch_fast<32, 32, 32, 16, 16, float>(live, n_live, s)
+                         : launch_cfg<32, 32, 32, 16, 16, float>(live, n_live, s);
+            }
         }
     }
     if (info) {
@@ -285,7 +499,6 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
         info->flops = flops;
         info->bytes = bytes;
     }
-    (void)t64;
     return e;
 }
 
