@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-trace", action="store_true")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU oracle work")
+    p.add_argument("--calib-copy", action="store_true",
+                   help="run one 512 MiB device-to-device copy first (HBM counter calibration)")
     return p.parse_args()
 
 
@@ -92,6 +94,24 @@ def cpu_baseline(kind: str, leaf: int, seed: int, budget_s: float):
     }
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when that summary is absent or the kernel's source file
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            rec = json.load(f).get(kernel)
+        if not rec:
+            return None
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def roofline_from_trace(recs, n_steps: int):
     """Dominant kernel = largest total traced time; achieved = its algorithmic
     flops per launch / its average launch duration."""
@@ -117,7 +137,8 @@ def roofline_from_trace(recs, n_steps: int):
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": None,
+        "traffic": measured_traffic(name),
+        "algorithmic_bytes_per_launch": d["bytes"] / d["count"],
         "avg_launch_ms": round(avg_ms, 5),
         "flops_per_launch": flops_per_launch,
         "launches": d["count"],
@@ -144,6 +165,13 @@ def main():
     del a_host
     dX = torch.empty_like(dA)
     stream = torch.cuda.current_stream()
+
+    if args.calib_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         if args.mode == "fp64":

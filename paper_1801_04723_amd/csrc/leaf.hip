@@ -39,118 +39,226 @@ __device__ inline bool better(double ov, int oi, double v, int i) {
     return ov > v || (ov == v && oi < i);
 }
 
-// ---------------------------------------------------------------- tier 1 ---
-template <int R, typename TI, typename TO>
-__global__ void __launch_bounds__(256)
-    leaf_small(const TI *__restrict__ in, int64_t ldi, TO *__restrict__ out, int64_t ldo, int L,
-               int col0, int *status) {
-    __shared__ double colbuf[2][128];
-    __shared__ double rowbuf[2][128];
-    __shared__ int rsel[128];
-    __shared__ int rinv[128];
+// ---------------------------------------------------------- wave helpers ---
+// DPP control words (GFX9 encoding).
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(x) & 0xffffffff), CTRL,
+                                               0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(x) >> 32), CTRL, 0xf,
+                                               0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline double readlane_f64(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Maximum over the 64 lanes of a wave (every lane receives it).  Keys are
+// finite (no NaN), so max is exact and order independent.
+__device__ inline double wave_max(double x) {
+    x = fmax(x, dpp_f64<kDppQuadXor1>(x));
+    x = fmax(x, dpp_f64<kDppQuadXor2>(x));
+    x = fmax(x, dpp_f64<kDppHalfMirror>(x));
+    x = fmax(x, dpp_f64<kDppMirror>(x));
+    const double a = fmax(readlane_f64(x, 0), readlane_f64(x, 16));
+    const double b = fmax(readlane_f64(x, 32), readlane_f64(x, 48));
+    return fmax(a, b);
+}
+
+// ------------------------------------------------------------ 2-D kernel ---
+// One workgroup of 16*TR threads eliminates a block of L <= TR*RR rows and
+// nb <= 16*RC columns held in registers: thread (tr, tc) owns rows tr + TR*r
+// and columns tc + 16*q.  A step:
+//   1. the owners of column c publish it to LDS (its register slot restarts
+//      as the implicit unit column);
+//   2. every wave finds the pivot redundantly: key |v| of each unused row
+//      (-0.5 for non-finite values, -1 for used rows), a DPP max over the
+//      wave, and the smallest row index holding the maximum via ballots;
+//   3. the owners of the pivot row publish it scaled by 1/pivot;
+//   4. every thread applies the rank-1 update to its registers.
+// WHOLE = true : the block is a whole leaf (columns = rows), read from `in`
+//                and written to `out` with the pivot permutation applied.
+// WHOLE = false: the block is one column panel of a blocked elimination on
+//                the FP64 scratch copy Z; the kernel writes the panel back,
+//                its transformation U' = U - E, the used-row flags and the
+//                gathered pivot rows Q of the other columns.
+struct LeafArgs {
+    const void *in;
+    int64_t ldi;
+    void *out;
+    int64_t ldo;
+    int L, col0;
+    int *status;
+    // panel mode
+    double *Z;
+    int64_t ldz;
+    int k0, nb;
+    int *used, *rsel;
+    double *Up, *Q;
+};
+
+template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
+__global__ void __launch_bounds__(16 * TR) leaf_gj2d(LeafArgs a) {
+    constexpr int NT = 16 * TR;
+    constexpr int LMAX = TR * RR;
+    constexpr int NBMAX = 16 * RC;
+    constexpr int CPL = LMAX / 64;
+    static_assert(CPL * 64 == LMAX, "rows must cover whole waves");
+    __shared__ double colbuf[2][LMAX];
+    __shared__ double rowbuf[2][NBMAX];
+    __shared__ int pivstep[LMAX];  // step at which a row was the pivot, or -1
+    __shared__ int prow_s[NBMAX];  // pivot row of each step
     const int t = threadIdx.x, tr = t >> 4, tc = t & 15, lane = t & 63;
+    const int L = a.L;
+    const int k0 = WHOLE ? 0 : a.k0;
+    const int nb = WHOLE ? a.L : a.nb;
 
-    double z[R][R];
+    for (int i = t; i < LMAX; i += NT) pivstep[i] = -1;
+    double z[RR][RC];
 #pragma unroll
-    for (int a = 0; a < R; ++a)
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
-            const int i = tr + 16 * a, j = tc + 16 * b;
-            z[a][b] = (i < L && j < L) ? (double)in[i + (int64_t)j * ldi] : 0.0;
+        for (int q = 0; q < RC; ++q) {
+            const int row = tr + TR * r, col = tc + 16 * q;
+            double v = 0.0;
+            if (row < L && col < nb) {
+                if (WHOLE)
+                    v = (double)static_cast<const TI *>(a.in)[row + (int64_t)col * a.ldi];
+                else
+                    v = a.Z[row + (int64_t)(k0 + col) * a.ldz];
+            }
+            z[r][q] = v;
         }
-    // Rows lane and lane + 64 are this lane's pivot candidates in the
-    // (redundant, per wave) argmax; padding rows never qualify.
-    bool u0 = lane >= L, u1 = (lane + 64) >= L;
+    bool usd[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int row = lane + 64 * j;
+        usd[j] = row >= L || (!WHOLE && k0 > 0 && a.used[row] != 0);
+    }
     int bad = 0;
+    __syncthreads();
 
 #pragma unroll
-    for (int kb = 0; kb < R; ++kb) {
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k = kb * 16 + kk;
-            if (k >= L) break;
-            const int buf = k & 1;
-            // column k to LDS; its slot restarts from the (implicit) unit column
-            if (tc == kk) {
+    for (int cb = 0; cb < RC; ++cb) {
+        for (int cc = 0; cc < 16; ++cc) {
+            const int c = cb * 16 + cc;
+            if (c >= nb) break;
+            const int buf = c & 1;
+            if (tc == cc) {
 #pragma unroll
-                for (int a = 0; a < R; ++a) {
-                    colbuf[buf][tr + 16 * a] = z[a][kb];
-                    z[a][kb] = 0.0;
+                for (int r = 0; r < RR; ++r) {
+                    colbuf[buf][tr + TR * r] = z[r][cb];
+                    z[r][cb] = 0.0;
                 }
             }
             __syncthreads();
-            const double v0 = colbuf[buf][lane];
-            const double v1 = colbuf[buf][lane + 64];
-            const double f0 = fabs(v0), f1 = fabs(v1);
-            const int nf = (!u0 && !(f0 <= DBL_MAX)) || (!u1 && !(f1 <= DBL_MAX));
-            // key: |v| for usable candidates, -0.5 for non-finite ones (so an
-            // unused row is always chosen and the pivot order stays a
-            // permutation even when the step fails), -1 for used rows
-            double best = u0 ? -1.0 : (f0 <= DBL_MAX ? f0 : -0.5);
-            int bi = lane;
-            const double c1 = u1 ? -1.0 : (f1 <= DBL_MAX ? f1 : -0.5);
-            if (c1 > best) {
-                best = c1;
-                bi = lane + 64;
+            double key[CPL];
+            int nf = 0;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) {
+                const double av = fabs(colbuf[buf][lane + 64 * j]);
+                const bool fin = av <= DBL_MAX;
+                nf |= (!usd[j] && !fin);
+                key[j] = usd[j] ? -1.0 : (fin ? av : -0.5);
             }
+            double lm = key[0];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off);
-                const int oi = __shfl_xor(bi, off);
-                if (better(ob, oi, best, bi)) {
-                    best = ob;
-                    bi = oi;
-                }
+            for (int j = 1; j < CPL; ++j) lm = fmax(lm, key[j]);
+            const double best = wave_max(lm);
+            int p = 0;
+#pragma unroll
+            for (int j = CPL - 1; j >= 0; --j) {
+                const unsigned long long m = __ballot(key[j] == best);
+                if (m) p = 64 * j + __builtin_ctzll(m);
             }
-            const int p = __builtin_amdgcn_readfirstlane(bi);
-            const bool fail = __any(nf) || !(best > 0.0);
-            if (fail && bad == 0) bad = k + 1;
-            if (lane == p) u0 = true;
-            if (lane + 64 == p) u1 = true;
-            // the owners of row p publish it scaled by 1/pivot
-            if (tr == (p & 15)) {
-                const int ap = p >> 4;
+            p = __builtin_amdgcn_readfirstlane(p);
+            if ((__any(nf) || !(best > 0.0)) && bad == 0) bad = c + 1;
 #pragma unroll
-                for (int a = 0; a < R; ++a) {
-                    if (a == ap) {
-                        const double pinv = 1.0 / colbuf[buf][p];
+            for (int j = 0; j < CPL; ++j)
+                if (lane + 64 * j == p) usd[j] = true;
+            const double pinv = 1.0 / colbuf[buf][p];
+            if (tr == p % TR) {
+                const int rp = p / TR;
 #pragma unroll
-                        for (int b = 0; b < R; ++b) {
-                            rowbuf[buf][tc + 16 * b] = z[a][b] * pinv;
-                            z[a][b] = 0.0;
+                for (int r = 0; r < RR; ++r) {
+                    if (r == rp) {
+#pragma unroll
+                        for (int q = 0; q < RC; ++q) {
+                            rowbuf[buf][tc + 16 * q] = z[r][q] * pinv;
+                            z[r][q] = 0.0;
                         }
-                        if (tc == kk) rowbuf[buf][k] = pinv;
+                        if (tc == cc) rowbuf[buf][c] = pinv;
                     }
                 }
             }
-            __syncthreads();
-            double f[R], rv[R];
-#pragma unroll
-            for (int a = 0; a < R; ++a) f[a] = (tr + 16 * a == p) ? -1.0 : colbuf[buf][tr + 16 * a];
-#pragma unroll
-            for (int b = 0; b < R; ++b) rv[b] = rowbuf[buf][tc + 16 * b];
-#pragma unroll
-            for (int a = 0; a < R; ++a)
-#pragma unroll
-                for (int b = 0; b < R; ++b) z[a][b] = fma(-f[a], rv[b], z[a][b]);
             if (t == 0) {
-                rsel[k] = p;
-                rinv[p] = k;
+                pivstep[p] = c;
+                prow_s[c] = p;
             }
+            __syncthreads();
+            double f[RR], rv[RC];
+#pragma unroll
+            for (int r = 0; r < RR; ++r) f[r] = (tr + TR * r == p) ? -1.0 : colbuf[buf][tr + TR * r];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) rv[q] = rowbuf[buf][tc + 16 * q];
+#pragma unroll
+            for (int r = 0; r < RR; ++r)
+#pragma unroll
+                for (int q = 0; q < RC; ++q) z[r][q] = fma(-f[r], rv[q], z[r][q]);
         }
     }
     __syncthreads();
+    if (WHOLE) {
+        // X[rinv[i]][r[c]] = Z[i][c]  with r[c] = prow_s[c], rinv[i] = pivstep[i]
+        TO *out = static_cast<TO *>(a.out);
 #pragma unroll
-    for (int a = 0; a < R; ++a)
+        for (int r = 0; r < RR; ++r)
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
-            const int i = tr + 16 * a, c = tc + 16 * b;
-            if (i < L && c < L) {
-                const int ri = rinv[i], rc = rsel[c];
-                if ((unsigned)ri < (unsigned)L && (unsigned)rc < (unsigned)L)
-                    out[ri + (int64_t)rc * ldo] = (TO)z[a][b];
+            for (int q = 0; q < RC; ++q) {
+                const int row = tr + TR * r, col = tc + 16 * q;
+                if (row < L && col < L) {
+                    const int ri = pivstep[row], rc = prow_s[col];
+                    if ((unsigned)ri < (unsigned)L && (unsigned)rc < (unsigned)L)
+                        out[ri + (int64_t)rc * a.ldo] = (TO)z[r][q];
+                }
+            }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+                const int row = tr + TR * r, col = tc + 16 * q;
+                if (row < L && col < nb) {
+                    a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[r][q];
+                    a.Up[row + (int64_t)col * L] = z[r][q] - ((pivstep[row] == col) ? 1.0 : 0.0);
+                }
+            }
+        for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = prow_s[c];
+        for (int row = t; row < L; row += NT) {
+            if (k0 == 0)
+                a.used[row] = pivstep[row] >= 0 ? 1 : 0;
+            else if (pivstep[row] >= 0)
+                a.used[row] = 1;
+        }
+        if (nb < L) {
+            const int64_t total = (int64_t)nb * L;
+            for (int64_t e = t; e < total; e += NT) {
+                const int c = (int)(e % nb), j = (int)(e / nb);
+                if (j >= k0 && j < k0 + nb) continue;
+                a.Q[c + (int64_t)j * nb] = a.Z[prow_s[c] + (int64_t)j * a.ldz];
             }
         }
-    if (t == 0 && bad) atomicMin(status, col0 + bad);
+    }
+    if (t == 0 && bad) atomicMin(a.status, a.col0 + k0 + bad);
 }
 
 // ---------------------------------------------------------------- tier 2 ---
@@ -338,32 +446,20 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------- launch ---
-template <int R, typename TI, typename TO>
-hipError_t small_launch(const void *in, int64_t ldi, void *out, int64_t ldo, int L, int col0,
-                        int *status, hipStream_t s) {
-    hipLaunchKernelGGL((leaf_small<R, TI, TO>), dim3(1), dim3(256), 0, s,
-                       static_cast<const TI *>(in), ldi, static_cast<TO *>(out), ldo, L, col0,
-                       status);
+template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
+hipError_t gj2d_launch(const LeafArgs &la, hipStream_t s) {
+    hipLaunchKernelGGL((leaf_gj2d<TR, RR, RC, WHOLE, TI, TO>), dim3(1), dim3(16 * TR), 0, s, la);
     return hipGetLastError();
 }
 
 template <typename TI, typename TO>
-hipError_t small_dispatch(const void *in, int64_t ldi, void *out, int64_t ldo, int L, int col0,
-                          int *status, hipStream_t s, const char **name) {
-    if (L <= 16) {
-        *name = "leaf_gj_regs_16";
-        return small_launch<1, TI, TO>(in, ldi, out, ldo, L, col0, status, s);
-    }
-    if (L <= 32) {
-        *name = "leaf_gj_regs_32";
-        return small_launch<2, TI, TO>(in, ldi, out, ldo, L, col0, status, s);
-    }
-    if (L <= 64) {
+hipError_t whole_dispatch(const LeafArgs &la, hipStream_t s, const char **name) {
+    if (la.L <= 64) {
         *name = "leaf_gj_regs_64";
-        return small_launch<4, TI, TO>(in, ldi, out, ldo, L, col0, status, s);
+        return gj2d_launch<16, 4, 4, true, TI, TO>(la, s);
     }
     *name = "leaf_gj_regs_128";
-    return small_launch<8, TI, TO>(in, ldi, out, ldo, L, col0, status, s);
+    return gj2d_launch<32, 4, 8, true, TI, TO>(la, s);
 }
 
 int panel_width(int64_t L) {
@@ -410,12 +506,20 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
     if (L <= 128) {
         LaunchInfo li{"leaf_gj_regs", 2.0 * Ld * Ld * Ld, 16.0 * Ld * Ld};
         cb(li, 0);
+        LeafArgs la{};
+        la.in = in;
+        la.ldi = ldi;
+        la.out = out;
+        la.ldo = ldo;
+        la.L = L;
+        la.col0 = (int)col0;
+        la.status = status;
         hipError_t e;
         const char *name = "leaf_gj_regs";
         if (in_dt == kF64 && out_dt == kF64)
-            e = small_dispatch<double, double>(in, ldi, out, ldo, L, (int)col0, status, s, &name);
+            e = whole_dispatch<double, double>(la, s, &name);
         else if (in_dt == kF32 && out_dt == kF32)
-            e = small_dispatch<float, float>(in, ldi, out, ldo, L, (int)col0, status, s, &name);
+            e = whole_dispatch<float, float>(la, s, &name);
         else
             return hipErrorInvalidValue;
         li.name = name;
@@ -452,15 +556,34 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
     for (int k0 = 0; k0 < L; k0 += nb) {
         const int w = (L - k0 < nb) ? (L - k0) : nb;
         PanelArgs pa{Z, (int64_t)L, L, k0, w, (int)col0, used, rsel, Up, status};
+        const bool fused = L <= 512;  // the 2-D panel kernel also gathers Q
         {
             LaunchInfo li{"leaf_gj_panel", 2.0 * Ld * w * w, 16.0 * Ld * w};
             cb(li, 0);
-            hipError_t e = panel_launch(pa, s);
+            hipError_t e;
+            if (fused) {
+                LeafArgs la{};
+                la.L = L;
+                la.col0 = (int)col0;
+                la.status = status;
+                la.Z = Z;
+                la.ldz = L;
+                la.k0 = k0;
+                la.nb = w;
+                la.used = used;
+                la.rsel = rsel;
+                la.Up = Up;
+                la.Q = Q;
+                e = (L <= 256) ? gj2d_launch<16, 16, 4, false, double, double>(la, s)
+                               : gj2d_launch<32, 16, 4, false, double, double>(la, s);
+            } else {
+                e = panel_launch(pa, s);
+            }
             cb(li, 1);
             if (e != hipSuccess) return e;
         }
         if (w == L) break;
-        {
+        if (!fused) {
             LaunchInfo li{"leaf_gather_q", 0.0, 16.0 * Ld * w};
             cb(li, 0);
             const int gb = (int)(((int64_t)L * w + 255) / 256);
