@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs g) {
 // agree).  B is staged k-contiguous (Bs[n][k]) so that a lane fetches its KQ
 // B values with 16-byte LDS reads; A is staged m-contiguous (As[k][m]).
 template <int BM, int BN, int BK, int WM, int WN, typename T>
-__global__ void __launch_bounds__(256) gemm_fast(GroupArgs g) {
+__global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs g) {
     constexpr int NT = 256;
     constexpr int VW = 16 / sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(VW)));
