@@ -13,18 +13,18 @@
 // augmented [A | I] would carry).  With r[k] = pivot row of step k and
 // rinv[r[k]] = k, the inverse is  X[rinv[i]][r[c]] = Z[i][c].
 //
-// Tier 1 (L <= 128): one workgroup of 256 threads holds the whole block in
-//   registers, cyclically distributed (thread (tr, tc) owns rows tr + 16a and
-//   columns tc + 16b).  A step costs two barriers: the owners of column k
-//   publish it to LDS, every wave finds the pivot redundantly with a wave
-//   reduction, the owners of the pivot row publish the scaled row, and every
-//   thread applies the rank-1 update to its registers.
+// Tier 1 (L <= 128): one workgroup holds the whole block in registers,
+//   cyclically distributed (thread (tr, tc) of a TR x 16 grid owns rows
+//   tr + TR*a and columns tc + 16b).  A step costs two barriers: the owners of
+//   column k publish it to LDS, every wave finds the pivot redundantly (DPP
+//   max, then ballots for the smallest row index), the owners of the pivot
+//   row publish the scaled row, and every thread applies the rank-1 update.
 // Tier 2 (L > 128): blocked Gauss-Jordan over column panels of width NB.  One
-//   workgroup eliminates a panel (all L rows x NB columns in registers) and
-//   emits the panel's transformation U' = U - E (E = unit entries at the
-//   pivot rows); the columns outside the panel are then updated by one
-//   grouped matrix-core product  Z[:, out] += U' * Z[pivot rows, out].
-//   A final pass writes the permuted result.
+//   workgroup eliminates a panel (all L rows x NB columns in registers, the
+//   same 2-D kernel) and emits the panel's transformation U' = U - E (E =
+//   unit entries at the pivot rows) and the pivot rows Q of the other
+//   columns; those columns are then updated by one grouped matrix-core
+//   product  Z[:, out] += U' * Q.  A final pass writes the permuted result.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -250,11 +250,11 @@ __global__ void __launch_bounds__(16 * TR) leaf_gj2d(LeafArgs a) {
                 a.used[row] = 1;
         }
         if (nb < L) {
-            const int64_t total = (int64_t)nb * L;
-            for (int64_t e = t; e < total; e += NT) {
-                const int c = (int)(e % nb), j = (int)(e / nb);
-                if (j >= k0 && j < k0 + nb) continue;
-                a.Q[c + (int64_t)j * nb] = a.Z[prow_s[c] + (int64_t)j * a.ldz];
+            // rows of Q (the pivot rows) in lane order, one column per pass
+            for (int j = t / NBMAX; j < L; j += NT / NBMAX) {
+                const int c = t % NBMAX;
+                if (c < nb && (j < k0 || j >= k0 + nb))
+                    a.Q[c + (int64_t)j * nb] = a.Z[prow_s[c] + (int64_t)j * a.ldz];
             }
         }
     }
@@ -452,6 +452,12 @@ hipError_t gj2d_launch(const LeafArgs &la, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Threads per row group of the 2-D kernel for whole leaves of order <= 128
+// and for panels of leaves of order <= 256 (measured best: 32, i.e. 512
+// threads, on MI355X).
+constexpr int kLeaf128TR = 32;
+constexpr int kPanel256TR = 32;
+
 template <typename TI, typename TO>
 hipError_t whole_dispatch(const LeafArgs &la, hipStream_t s, const char **name) {
     if (la.L <= 64) {
@@ -459,7 +465,7 @@ hipError_t whole_dispatch(const LeafArgs &la, hipStream_t s, const char **name) 
         return gj2d_launch<16, 4, 4, true, TI, TO>(la, s);
     }
     *name = "leaf_gj_regs_128";
-    return gj2d_launch<32, 4, 8, true, TI, TO>(la, s);
+    return gj2d_launch<kLeaf128TR, 128 / kLeaf128TR, 8, true, TI, TO>(la, s);
 }
 
 int panel_width(int64_t L) {
@@ -574,8 +580,10 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                 la.rsel = rsel;
                 la.Up = Up;
                 la.Q = Q;
-                e = (L <= 256) ? gj2d_launch<16, 16, 4, false, double, double>(la, s)
-                               : gj2d_launch<32, 16, 4, false, double, double>(la, s);
+                if (L <= 256)
+                    e = gj2d_launch<kPanel256TR, 256 / kPanel256TR, 4, false, double, double>(la, s);
+                else
+                    e = gj2d_launch<64, 8, 4, false, double, double>(la, s);
             } else {
                 e = panel_launch(pa, s);
             }
