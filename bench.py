@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-trace", action="store_true")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU oracle work")
+    p.add_argument("--serve-seconds", type=float, default=10.0,
+                   help="length of the open-loop serving run (0 disables it)")
+    p.add_argument("--serve-rate", type=float, default=200.0, help="serving arrival rate, req/s")
     p.add_argument("--calib-copy", action="store_true",
                    help="run one 512 MiB device-to-device copy first (HBM counter calibration)")
     return p.parse_args()
@@ -92,6 +95,20 @@ def cpu_baseline(kind: str, leaf: int, seed: int, budget_s: float):
         "sample": f"oracle Strassen recursion (Alg. 1, FP64, OpenMP) on {kind} n={n_s} "
                   f"leaf={min(leaf, n_s)}: one run, {t:.2f} s",
     }
+
+
+def serving(rate: float, seconds: float):
+    """Open-loop serving run: Poisson arrivals at `rate` for `seconds`, orders
+    log-uniform in [64, 4096] padded to 64, half diagonally dominant and half
+    SPD (kappa log-uniform in [10, 1e4]), 70% mixed precision with 2 Newton
+    steps and 30% FP64, leaf 128; p50/p99 latency from arrival to completion."""
+    import workloads as W
+    from paper_1801_04723_amd import serve
+    trace = W.serving_trace(rate=rate, duration=seconds, seed=5)
+    st = serve.run_trace(trace, leaf=128, ns_steps=2)
+    st["workload"] = (f"Poisson {rate:g} req/s for {seconds:g} s, n log-uniform 64..4096 (x64), "
+                      "50% diag-dominant / 50% SPD, 70% mixed FP32+2 Newton / 30% FP64, leaf 128")
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
 
 
 def measured_traffic(kernel: str):
@@ -233,6 +250,8 @@ def main():
         out["kernel_breakdown"] = breakdown
     else:
         out["roofline"] = None
+    if args.serve_seconds > 0:
+        out["serving"] = serving(args.serve_rate, args.serve_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.kind, leaf, seed, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -135,6 +135,47 @@ const char *spin_strerror(int code);
 /* Frees every cached workspace and captured graph (waits for the device). */
 void spin_release(void);
 
+/* ---- batched inversion and continuous batching ---------------------------- */
+/* Inverts `count` independent matrices (each column-major, its own order n[i]
+ * and leading dimensions; mode[i] = SPIN_FP64 or SPIN_MIXED_FP32 with
+ * `ns_steps` refinement steps) with cross-request batching: at each step the
+ * block products of all requests run in grouped matrix-core launches and
+ * their leaves in one batched leaf launch.  Every request's result is bit for
+ * bit the one spin_invert / spin_invert_mixed would give it alone.  Waits for
+ * the stream; info[i] (optional) receives request i's numerical status. */
+int spin_invert_batch(int64_t count, const double *const *A, const int64_t *n,
+                      const int64_t *lda, double *const *Ainv, const int64_t *ldx,
+                      const int *mode, int64_t leaf, int ns_steps, int *info,
+                      spin_stream_t stream);
+
+/* Continuous-batching server (one host thread drives it).  The server owns a
+ * device workspace pool of pool_bytes (allocated at the first tick); requests
+ * wait in a FIFO queue and are admitted when one of max_active slots is free
+ * and their workspace (spin_server_request_bytes) fits in the pool.  Each
+ * tick launches the next step of every admitted request on `stream`, grouped
+ * across requests as in spin_invert_batch; requests finish independently and
+ * their pool space is reused by the queue.  A and Ainv of a submitted request
+ * must stay valid until spin_server_poll reports it. */
+typedef struct spin_server spin_server;
+spin_server *spin_server_create(size_t pool_bytes, int max_active, int64_t leaf, int ns_steps);
+void spin_server_destroy(spin_server *srv);
+/* Queues one request (returns 0, or SPIN_E_* when the arguments are invalid or
+ * the request could never fit in the pool). */
+int spin_server_submit(spin_server *srv, const double *A, int64_t n, int64_t lda, double *Ainv,
+                       int64_t ldx, int mode, int64_t tag);
+/* Host only: admits queued requests that fit (returns how many). */
+int spin_server_admit(spin_server *srv);
+/* Admits, then enqueues one step of every admitted request; returns the
+ * number of admitted, unfinished requests or a negative SPIN_E_* code. */
+int spin_server_tick(spin_server *srv, spin_stream_t stream);
+/* Non-blocking: writes up to cap (tag, status) pairs of requests whose work
+ * has completed since the last poll and frees their pool space; returns the
+ * count. */
+int64_t spin_server_poll(spin_server *srv, int64_t *tags, int *info, int64_t cap);
+int spin_server_stats(spin_server *srv, int64_t *queued, int64_t *active, size_t *pool_used);
+/* Pool bytes one request of order n needs (0 for invalid arguments). */
+size_t spin_server_request_bytes(int64_t n, int64_t leaf, int mode);
+
 /* ---- schedule introspection (host only, no GPU needed) -------------------- */
 /* One step of the recursion schedule as the executor runs it (S-form: the
  * Schur complement S = A22 - A21 A11^-1 A12 = -V is formed and inverted

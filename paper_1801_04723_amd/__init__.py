@@ -122,6 +122,27 @@ def lib() -> ctypes.CDLL:
         L.spin_trace_enable.restype = ctypes.c_int
         L.spin_trace_collect.argtypes = [ctypes.POINTER(TraceRec), _i64]
         L.spin_trace_collect.restype = _i64
+        P64 = ctypes.POINTER(_i64)
+        L.spin_invert_batch.argtypes = [_i64, ctypes.POINTER(_vp), P64, P64, ctypes.POINTER(_vp), P64,
+                                        ctypes.POINTER(ctypes.c_int), _i64, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int), _vp]
+        L.spin_invert_batch.restype = ctypes.c_int
+        L.spin_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, _i64, ctypes.c_int]
+        L.spin_server_create.restype = _vp
+        L.spin_server_destroy.argtypes = [_vp]
+        L.spin_server_destroy.restype = None
+        L.spin_server_submit.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, ctypes.c_int, _i64]
+        L.spin_server_submit.restype = ctypes.c_int
+        L.spin_server_admit.argtypes = [_vp]
+        L.spin_server_admit.restype = ctypes.c_int
+        L.spin_server_tick.argtypes = [_vp, _vp]
+        L.spin_server_tick.restype = ctypes.c_int
+        L.spin_server_poll.argtypes = [_vp, P64, ctypes.POINTER(ctypes.c_int), _i64]
+        L.spin_server_poll.restype = _i64
+        L.spin_server_stats.argtypes = [_vp, P64, P64, ctypes.POINTER(ctypes.c_size_t)]
+        L.spin_server_stats.restype = ctypes.c_int
+        L.spin_server_request_bytes.argtypes = [_i64, _i64, ctypes.c_int]
+        L.spin_server_request_bytes.restype = ctypes.c_size_t
         _lib = L
     return _lib
 
@@ -310,3 +331,94 @@ def trace_collect() -> list[dict]:
     cnt = L.spin_trace_collect(arr, 65536)
     return [dict(kernel=r.kernel.decode(), ms=r.ms, flops=r.flops, bytes=r.bytes, level=r.level)
             for r in arr[: min(int(cnt), 65536)]]
+
+
+# ------------------------------------------------------------ batch / server
+def invert_batch(mats, leaf: int, modes=None, ns_steps: int = 2, outs=None, stream=None):
+    """Inverts a list of square float64 GPU matrices with cross-request
+    batching (spin_invert_batch); waits.  Returns (list of inverses, infos)."""
+    count = len(mats)
+    modes = [FP64] * count if modes is None else [_mode(m) for m in modes]
+    if outs is None:
+        outs = [_empty_like_layout(a, _layout(a)[1]) for a in mats]
+    ptr_a = (_vp * count)(*[a.data_ptr() for a in mats])
+    ptr_x = (_vp * count)(*[x.data_ptr() for x in outs])
+    ns = (_i64 * count)(*[a.shape[0] for a in mats])
+    lda = (_i64 * count)(*[_layout(a)[0] for a in mats])
+    ldx = (_i64 * count)(*[_layout(x)[0] for x in outs])
+    md = (ctypes.c_int * count)(*modes)
+    info = (ctypes.c_int * count)()
+    for a, x in zip(mats, outs):
+        _check_square(a)
+        if _layout(a)[1] != _layout(x)[1]:
+            raise ValueError("output must have the same memory order as the input")
+    rc = lib().spin_invert_batch(count, ptr_a, ns, lda, ptr_x, ldx, md, int(leaf), int(ns_steps),
+                                 info, _stream(stream))
+    if rc != 0:
+        raise SpinError(rc, "spin_invert_batch")
+    return outs, [int(v) for v in info]
+
+
+def server_request_bytes(n: int, leaf: int, mode=FP64) -> int:
+    return int(lib().spin_server_request_bytes(int(n), int(leaf), _mode(mode)))
+
+
+class Server:
+    """Continuous-batching server over the C ABI (one host thread).
+
+    submit() queues a request (A and its output stay referenced until the
+    request is reported by poll()); tick() admits what fits and launches one
+    step of every admitted request; poll() returns finished (tag, status)."""
+
+    def __init__(self, pool_bytes: int, max_active: int, leaf: int, ns_steps: int = 2):
+        self._h = lib().spin_server_create(int(pool_bytes), int(max_active), int(leaf), int(ns_steps))
+        if not self._h:
+            raise ValueError("invalid server parameters")
+        self._keep = {}
+
+    def submit(self, a, out, mode=FP64, tag: int = 0) -> None:
+        lda, oa = _layout(a)
+        ldx, ox = _layout(out)
+        if oa != ox:
+            raise ValueError("output must have the same memory order as the input")
+        rc = lib().spin_server_submit(self._h, a.data_ptr(), a.shape[0], lda, out.data_ptr(), ldx,
+                                      _mode(mode), int(tag))
+        if rc != 0:
+            raise SpinError(rc, "spin_server_submit")
+        self._keep[int(tag)] = (a, out)
+
+    def admit(self) -> int:
+        return int(lib().spin_server_admit(self._h))
+
+    def tick(self, stream=None) -> int:
+        rc = lib().spin_server_tick(self._h, _stream(stream))
+        if rc < 0:
+            raise SpinError(rc, "spin_server_tick")
+        return rc
+
+    def poll(self, cap: int = 4096):
+        tags = (_i64 * cap)()
+        info = (ctypes.c_int * cap)()
+        cnt = lib().spin_server_poll(self._h, tags, info, cap)
+        out = [(int(tags[i]), int(info[i])) for i in range(cnt)]
+        for t, _ in out:
+            self._keep.pop(t, None)
+        return out
+
+    def stats(self):
+        q, a = _i64(0), _i64(0)
+        used = ctypes.c_size_t(0)
+        lib().spin_server_stats(self._h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(used))
+        return {"queued": q.value, "active": a.value, "pool_used": used.value}
+
+    def close(self) -> None:
+        if self._h:
+            lib().spin_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

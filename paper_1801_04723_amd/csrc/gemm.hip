@@ -52,15 +52,28 @@ struct Mma<float> {
     __device__ static inline int ncol(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
+// Up to N independent products in one grid: workgroup b belongs to the
+// problem whose tile range [tile_start[q], tile_start[q+1]) contains b.
+template <int N>
 struct GroupArgs {
-    GemmProb p[kMaxGroup];
+    GemmProb p[N];
     int32_t count;
-    int32_t tile_start[kMaxGroup + 1];
-    int32_t tiles_m[kMaxGroup];
+    int32_t tile_start[N + 1];
+    int32_t tiles_m[N];
 };
 
-template <int BM, int BN, int BK, int WM, int WN, typename T>
-__global__ void __launch_bounds__(256) gemm_kernel(GroupArgs g) {
+// Problem of workgroup `bid` (uniform scan over the prefix sums).
+template <int N>
+__device__ inline int group_member(const GroupArgs<N> &g, int bid) {
+    int pi = 0;
+#pragma unroll
+    for (int q = 1; q < N; ++q)
+        if (q < g.count && bid >= g.tile_start[q]) pi = q;
+    return pi;
+}
+
+template <int BM, int BN, int BK, int WM, int WN, typename T, int NG>
+__global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
     constexpr int NT = 256;
     constexpr int WAVES_M = BM / WM;
     static_assert(WAVES_M * (BN / WN) == 4, "four waves per workgroup");
@@ -75,21 +88,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs g) {
     __shared__ T As[2][BK * A_LD];
     __shared__ T Bs[2][BK * B_LD];
 
-    // ---- which problem of the group and which tile --------------------------
     const int bid = blockIdx.x;
-    int pi = 0;
-#pragma unroll
-    for (int q = 1; q < kMaxGroup; ++q)
-        if (q < g.count && bid >= g.tile_start[q]) pi = q;
-    GemmProb P = g.p[0];
-    int tstart = g.tile_start[0], tiles_m = g.tiles_m[0];
-#pragma unroll
-    for (int q = 1; q < kMaxGroup; ++q)
-        if (pi == q) {
-            P = g.p[q];
-            tstart = g.tile_start[q];
-            tiles_m = g.tiles_m[q];
-        }
+    const int pi = group_member(g, bid);
+    const GemmProb P = g.p[pi];
+    const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
     const int t = bid - tstart;
     const int tm = t % tiles_m, tn = t / tiles_m;
 
@@ -213,8 +215,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs g) {
 // (any assignment of k to the four MFMA k-slots is valid as long as A and B
 // agree).  B is staged k-contiguous (Bs[n][k]) so that a lane fetches its KQ
 // B values with 16-byte LDS reads; A is staged m-contiguous (As[k][m]).
-template <int BM, int BN, int BK, int WM, int WN, typename T>
-__global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs g) {
+template <int BM, int BN, int BK, int WM, int WN, typename T, int NG>
+__global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
     constexpr int NT = 256;
     constexpr int VW = 16 / sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(VW)));
@@ -234,19 +236,9 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs g) {
     __shared__ __attribute__((aligned(16))) T Bs[2][BN * B_LD];
 
     const int bid = blockIdx.x;
-    int pi = 0;
-#pragma unroll
-    for (int q = 1; q < kMaxGroup; ++q)
-        if (q < g.count && bid >= g.tile_start[q]) pi = q;
-    GemmProb P = g.p[0];
-    int tstart = g.tile_start[0], tiles_m = g.tiles_m[0];
-#pragma unroll
-    for (int q = 1; q < kMaxGroup; ++q)
-        if (pi == q) {
-            P = g.p[q];
-            tstart = g.tile_start[q];
-            tiles_m = g.tiles_m[q];
-        }
+    const int pi = group_member(g, bid);
+    const GemmProb P = g.p[pi];
+    const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
     const int t = bid - tstart;
     const int tm = t % tiles_m, tn = t / tiles_m;
     const int M = P.m, N = P.n, K = P.k;
@@ -368,12 +360,13 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs g) {
     }
 }
 
-template <int BM, int BN, int BK, int WM, int WN, typename T>
-hipError_t launch_cfg(const GemmProb *probs, int count, hipStream_t s) {
-    GroupArgs g{};
+// One launch of up to N products that share a kernel configuration.
+template <bool FAST, int BM, int BN, int BK, int WM, int WN, typename T, int N>
+hipError_t launch_group(const GemmProb *probs, int count, hipStream_t s) {
+    GroupArgs<N> g{};
     g.count = count;
     int total = 0;
-    for (int q = 0; q < kMaxGroup; ++q) {
+    for (int q = 0; q < N; ++q) {
         if (q < count) {
             g.p[q] = probs[q];
             const int tm = (probs[q].m + BM - 1) / BM, tn = (probs[q].n + BN - 1) / BN;
@@ -386,113 +379,105 @@ hipError_t launch_cfg(const GemmProb *probs, int count, hipStream_t s) {
             g.tiles_m[q] = 1;
         }
     }
-    g.tile_start[kMaxGroup] = total;
+    g.tile_start[N] = total;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, T>), dim3(total), dim3(256), 0, s, g);
+    if constexpr (FAST)
+        hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
-int64_t tiles_for(const GemmProb *probs, int count, int bm, int bn) {
-    int64_t t = 0;
-    for (int q = 0; q < count; ++q)
-        t += (int64_t)((probs[q].m + bm - 1) / bm) * ((probs[q].n + bn - 1) / bn);
-    return t;
-}
-
-
+// K slab of the fast 128x128 kernel (FP64: 16 keeps two workgroups per CU;
+// FP32: 32).  Every other fast configuration uses 32.
 constexpr int kFastBK128 = 16;
+constexpr int fast_bk(int tile, int es) { return (tile == 128 && es == 8) ? kFastBK128 : 32; }
 
-// Conditions of the fast path for every product of a launch.
-bool fast_ok(const GemmProb *probs, int count, int vw, int bk) {
-    for (int q = 0; q < count; ++q) {
-        const GemmProb &p = probs[q];
-        if (p.k <= 0 || p.k % bk != 0 || p.m % vw != 0) return false;
-        if (p.lda % vw != 0 || p.ldb % vw != 0) return false;
-        if ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.B)) & 15) return false;
-    }
-    return true;
+// Kernel configuration of one product, a function of that product alone (its
+// shape, leading dimensions and alignment), so that a product is computed
+// bit for bit the same whether it is launched alone or grouped with others.
+struct Cfg {
+    int tile;   // 128, 64 or 32
+    bool fast;  // branch-free vector path
+    bool operator==(const Cfg &o) const { return tile == o.tile && fast == o.fast; }
+};
+
+Cfg choose_cfg(const GemmProb &p, int es) {
+    const int vw = 16 / es;
+    const int64_t t128 = (int64_t)((p.m + 127) / 128) * ((p.n + 127) / 128);
+    const int64_t t64 = (int64_t)((p.m + 63) / 64) * ((p.n + 63) / 64);
+    Cfg c;
+    c.tile = (t128 >= 192) ? 128 : (t64 >= 128) ? 64 : 32;
+    const int bk = fast_bk(c.tile, es);
+    c.fast = p.k > 0 && p.k % bk == 0 && p.m % vw == 0 && p.lda % vw == 0 && p.ldb % vw == 0 &&
+             ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.B)) & 15) == 0;
+    return c;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, typename T>
-hipError_t launch_fast(const GemmProb *probs, int count, hipStream_t s) {
-    GroupArgs g{};
-    g.count = count;
-    int total = 0;
-    for (int q = 0; q < kMaxGroup; ++q) {
-        if (q < count) {
-            g.p[q] = probs[q];
-            const int tm = (probs[q].m + BM - 1) / BM, tn = (probs[q].n + BN - 1) / BN;
-            g.tile_start[q] = total;
-            g.tiles_m[q] = tm > 0 ? tm : 1;
-            total += tm * tn;
-        } else {
-            g.p[q] = probs[0];
-            g.tile_start[q] = 1 << 30;
-            g.tiles_m[q] = 1;
-        }
-    }
-    g.tile_start[kMaxGroup] = total;
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T>), dim3(total), dim3(256), 0, s, g);
-    return hipGetLastError();
+template <typename T, int N>
+hipError_t launch_cfg(Cfg c, const GemmProb *probs, int count, hipStream_t s) {
+    constexpr int ES = sizeof(T);
+    if (c.tile == 128)
+        return c.fast ? launch_group<true, 128, 128, fast_bk(128, ES), 64, 64, T, N>(probs, count, s)
+                      : launch_group<false, 128, 128, 16, 64, 64, T, N>(probs, count, s);
+    if (c.tile == 64)
+        return c.fast ? launch_group<true, 64, 64, fast_bk(64, ES), 32, 32, T, N>(probs, count, s)
+                      : launch_group<false, 64, 64, 16, 32, 32, T, N>(probs, count, s);
+    return c.fast ? launch_group<true, 32, 32, fast_bk(32, ES), 16, 16, T, N>(probs, count, s)
+                  : launch_group<false, 32, 32, 32, 16, 16, T, N>(probs, count, s);
+}
+
+const char *cfg_name(Cfg c, DType dt) {
+    static const char *names[2][3][2] = {
+        {{"gemm_f64_128x128_edge", "gemm_f64_128x128"}, {"gemm_f64_64x64_edge", "gemm_f64_64x64"},
+         {"gemm_f64_32x32_edge", "gemm_f64_32x32"}},
+        {{"gemm_f32_128x128_edge", "gemm_f32_128x128"}, {"gemm_f32_64x64_edge", "gemm_f32_64x64"},
+         {"gemm_f32_32x32_edge", "gemm_f32_32x32"}}};
+    const int ti = c.tile == 128 ? 0 : c.tile == 64 ? 1 : 2;
+    return names[dt == kF64 ? 0 : 1][ti][c.fast ? 1 : 0];
 }
 
 }  // namespace
 
 hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s, LaunchInfo *info) {
-    if (count < 1 || count > kMaxGroup) return hipErrorInvalidValue;
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    const int esz = (dt == kF64) ? 8 : 4;
+    const double es = esz;
     // Products with an empty reduction still need their epilogue; drop only
-    // products with an empty output.
-    GemmProb live[kMaxGroup];
+    // products with an empty output.  Group the rest by configuration.
+    GemmProb part[kMaxBatch];
+    Cfg cfgs[kMaxBatch];
+    bool done[kMaxBatch];
     int n_live = 0;
     double flops = 0, bytes = 0;
-    const double es = (dt == kF64) ? 8.0 : 4.0;
     for (int q = 0; q < count; ++q) {
         if (probs[q].m <= 0 || probs[q].n <= 0) continue;
-        live[n_live++] = probs[q];
+        part[n_live] = probs[q];
+        cfgs[n_live] = choose_cfg(probs[q], esz);
+        done[n_live] = false;
+        ++n_live;
         const double m = probs[q].m, n = probs[q].n, k = probs[q].k;
         flops += 2.0 * m * n * k;
         bytes += es * (m * k + k * n + m * n + ((probs[q].beta != 0.0) ? m * n : 0.0));
     }
-    // Largest tile that still gives every compute unit work; small problems
-    // fall back to smaller tiles so that more workgroups run concurrently.
-    const int64_t t128 = tiles_for(live, n_live, 128, 128);
-    const int64_t t64 = tiles_for(live, n_live, 64, 64);
-    const int tile = (t128 >= 256) ? 128 : (t64 >= 256) ? 64 : 32;
-    const int bk = (tile == 128) ? kFastBK128 : 32;
-    const bool fast = n_live > 0 && fast_ok(live, n_live, dt == kF64 ? 2 : 4, bk);
     const char *name = "gemm_empty";
     hipError_t e = hipSuccess;
-    if (n_live > 0) {
-        if (dt == kF64) {
-            if (tile == 128) {
-                name = fast ? "gemm_f64_128x128" : "gemm_f64_128x128_edge";
-                e = fast ? launch_fast<128, 128, kFastBK128, 64, 64, double>(live, n_live, s)
-                         : launch_cfg<128, 128, 16, 64, 64, double>(live, n_live, s);
-            } else if (tile == 64) {
-                name = fast ? "gemm_f64_64x64" : "gemm_f64_64x64_edge";
-                e = fast ? launch_fast<64, 64, 32, 32, 32, double>(live, n_live, s)
-                         : launch_cfg<64, 64, 16, 32, 32, double>(live, n_live, s);
-            } else {
-                name = fast ? "gemm_f64_32x32" : "gemm_f64_32x32_edge";
-                e = fast ? launch_fast<32, 32, 32, 16, 16, double>(live, n_live, s)
-                         : launch_cfg<32, 32, 32, 16, 16, double>(live, n_live, s);
+    for (int q = 0; q < n_live && e == hipSuccess; ++q) {
+        if (done[q]) continue;
+        GemmProb grp[kMaxBatch];
+        int ng = 0;
+        for (int r = q; r < n_live; ++r)
+            if (!done[r] && cfgs[r] == cfgs[q]) {
+                grp[ng++] = part[r];
+                done[r] = true;
             }
-        } else {
-            if (tile == 128) {
-                name = fast ? "gemm_f32_128x128" : "gemm_f32_128x128_edge";
-                e = fast ? launch_fast<128, 128, 32, 64, 64, float>(live, n_live, s)
-                         : launch_cfg<128, 128, 16, 64, 64, float>(live, n_live, s);
-            } else if (tile == 64) {
-                name = fast ? "gemm_f32_64x64" : "gemm_f32_64x64_edge";
-                e = fast ? launch_fast<64, 64, 32, 32, 32, float>(live, n_live, s)
-                         : launch_cfg<64, 64, 16, 32, 32, float>(live, n_live, s);
-            } else {
-                name = fast ? "gemm_f32_32x32" : "gemm_f32_32x32_edge";
-                e = fast ? launch_fast<32, 32, 32, 16, 16, float>(live, n_live, s)
-                         : launch_cfg<32, 32, 32, 16, 16, float>(live, n_live, s);
-            }
-        }
+        name = cfg_name(cfgs[q], dt);
+        if (dt == kF64)
+            e = (ng <= 2) ? launch_cfg<double, 2>(cfgs[q], grp, ng, s)
+                          : launch_cfg<double, kMaxBatch>(cfgs[q], grp, ng, s);
+        else
+            e = (ng <= 2) ? launch_cfg<float, 2>(cfgs[q], grp, ng, s)
+                          : launch_cfg<float, kMaxBatch>(cfgs[q], grp, ng, s);
     }
     if (info) {
         info->name = name;

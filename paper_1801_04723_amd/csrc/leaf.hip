@@ -107,7 +107,7 @@ struct LeafArgs {
 };
 
 template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
-__global__ void __launch_bounds__(16 * TR) leaf_gj2d(LeafArgs a) {
+__device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a) {
     constexpr int NT = 16 * TR;
     constexpr int LMAX = TR * RR;
     constexpr int NBMAX = 16 * RC;
@@ -259,6 +259,28 @@ __global__ void __launch_bounds__(16 * TR) leaf_gj2d(LeafArgs a) {
         }
     }
     if (t == 0 && bad) atomicMin(a.status, a.col0 + k0 + bad);
+}
+
+template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
+__global__ void __launch_bounds__(16 * TR) leaf_gj2d(LeafArgs a) {
+    gj2d_run<TR, RR, RC, WHOLE, TI, TO>(a);
+}
+
+// Many independent whole leaves in one grid (one workgroup each); the same
+// device code as a single leaf, so every leaf's result is identical to the
+// one it gets when launched alone.
+template <int TR, int RR, int RC, typename TI, typename TO>
+__global__ void __launch_bounds__(16 * TR) leaf_gj2d_batch(LeafBatch b) {
+    const LeafItem &it = b.item[blockIdx.x];
+    LeafArgs a{};
+    a.in = it.in;
+    a.ldi = it.ldi;
+    a.out = it.out;
+    a.ldo = it.ldo;
+    a.L = (int)it.L;
+    a.col0 = (int)it.col0;
+    a.status = it.status;
+    gj2d_run<TR, RR, RC, true, TI, TO>(a);
 }
 
 // ---------------------------------------------------------------- tier 2 ---
@@ -630,6 +652,49 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
         cb(li, 1);
         return e;
     }
+}
+
+
+hipError_t leaf_batch_launch(const LeafItem *items, int count, DType dt, hipStream_t s,
+                             LaunchInfo *info) {
+    if (count < 0 || count > kMaxLeafBatch) return hipErrorInvalidValue;
+    double flops = 0, bytes = 0;
+    LeafBatch small{}, big{};
+    for (int i = 0; i < count; ++i) {
+        if (items[i].L < 1 || items[i].L > 128) return hipErrorInvalidValue;
+        const double L = (double)items[i].L;
+        flops += 2.0 * L * L * L;
+        bytes += 16.0 * L * L;
+        if (items[i].L <= 64)
+            small.item[small.count++] = items[i];
+        else
+            big.item[big.count++] = items[i];
+    }
+    hipError_t e = hipSuccess;
+    if (small.count) {
+        if (dt == kF64)
+            hipLaunchKernelGGL((leaf_gj2d_batch<16, 4, 4, double, double>), dim3(small.count),
+                               dim3(256), 0, s, small);
+        else
+            hipLaunchKernelGGL((leaf_gj2d_batch<16, 4, 4, float, float>), dim3(small.count),
+                               dim3(256), 0, s, small);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && big.count) {
+        if (dt == kF64)
+            hipLaunchKernelGGL((leaf_gj2d_batch<kLeaf128TR, 128 / kLeaf128TR, 8, double, double>),
+                               dim3(big.count), dim3(16 * kLeaf128TR), 0, s, big);
+        else
+            hipLaunchKernelGGL((leaf_gj2d_batch<kLeaf128TR, 128 / kLeaf128TR, 8, float, float>),
+                               dim3(big.count), dim3(16 * kLeaf128TR), 0, s, big);
+        e = hipGetLastError();
+    }
+    if (info) {
+        info->name = "leaf_gj_regs_batch";
+        info->flops = flops;
+        info->bytes = bytes;
+    }
+    return e;
 }
 
 }  // namespace spin

@@ -28,48 +28,17 @@
 
 #include "spin.h"
 #include "spin_kernels.hpp"
+#include "spin_plan.hpp"
 
 namespace spin {
-namespace {
 
 // ------------------------------------------------------------------ plan ----
-enum Buf { BUF_A = 0, BUF_X = 1, BUF_WS = 2 };
-
-struct Ref {
-    int buf;
-    int64_t off;
-    int64_t ld;
-};
-
-struct PGemm {
-    Ref a, b, c, d;
-    int64_t m, n, k;
-    double alpha, beta;
-    int add_identity;
-};
-
-struct POp {
-    int kind;  // 0 = products, 1 = leaf
-    int count;
-    int level;
-    PGemm g[2];
-    Ref in, out;
-    int64_t L, col0;
-};
-
-struct Plan {
-    int64_t n = 0, lda = 0, ldx = 0, leaf = 0;
-    std::vector<POp> ops;
-    int64_t ws_elems = 0;
-    int64_t max_leaf = 0;
-    double flops = 0;
-};
-
 // Order of the leading block when an order-m block is split: exact halving
 // for m = leaf * 2^k, otherwise the half rounded up to a multiple of 64 so
 // that block products stay aligned with the 64-wide tiles.
 int64_t split_order(int64_t m) { return m >= 128 ? 64 * ((m + 127) / 128) : (m + 1) / 2; }
 
+namespace {
 Ref sub(const Ref &r, int64_t i, int64_t j) { return Ref{r.buf, r.off + i + j * r.ld, r.ld}; }
 
 void push_products(Plan &P, int level, const PGemm &g0, const PGemm *g1) {
@@ -131,6 +100,8 @@ void plan_node(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level, in
     push_products(P, level, PGemm{III, C21, C11, C11, n1, n1, n2, -1.0, 1.0, 0}, nullptr);
 }
 
+}  // namespace
+
 Plan make_plan(int64_t n, int64_t lda, int64_t ldx, int64_t leaf) {
     Plan P;
     P.n = n;
@@ -140,6 +111,55 @@ Plan make_plan(int64_t n, int64_t lda, int64_t ldx, int64_t leaf) {
     plan_node(P, Ref{BUF_A, 0, lda}, Ref{BUF_X, 0, ldx}, n, 0, 0, 0);
     return P;
 }
+
+
+// ------------------------------------------------------------ workspace ----
+// Layout of a stream's workspace (bytes):
+//   [0, 256)          status words (int): 0 = pivot status, 1 = refinement status
+//   [256, 4096)       small doubles: 0..7 refinement norms, 8..15 misc norms
+//   [4096, +8 KiB)    Frobenius-norm partials
+//   then              recursion workspace, leaf scratch, mixed-mode buffers
+
+
+
+Layout layout_for(int64_t n, int64_t leaf, int mode, int64_t ws_elems, int64_t max_leaf) {
+    Layout L{};
+    const size_t es = (mode == SPIN_FP64) ? 8 : 4;
+    size_t off = kHdr;
+    L.rec_off = off;
+    L.rec_bytes = al256((size_t)ws_elems * es);
+    off += L.rec_bytes;
+    L.leaf_off = off;
+    L.leaf_bytes = al256(leaf_scratch_bytes(max_leaf));
+    off += L.leaf_bytes;
+    if (mode != SPIN_FP64) {
+        const size_t nn = (size_t)n * (size_t)n;
+        L.a32_off = off;
+        off += al256(nn * 4);
+        L.x32_off = off;
+        off += al256(nn * 4);
+        L.r_off = off;
+        off += al256(nn * 8);
+        L.xalt_off = off;
+        off += al256(nn * 8);
+    }
+    (void)leaf;
+    L.total = off;
+    return L;
+}
+
+
+GemmProb make_prob(char *const base[3], size_t es, const PGemm &g) {
+    const bool use_c = g.beta != 0.0;
+    auto at = [&](const Ref &r) -> void * { return base[r.buf] + (size_t)r.off * es; };
+    return GemmProb{at(g.a),          at(g.b),       use_c ? at(g.c) : nullptr,
+                    at(g.d),          g.a.ld,        g.b.ld,
+                    use_c ? g.c.ld : 1, g.d.ld,      (int32_t)g.m,
+                    (int32_t)g.n,     (int32_t)g.k,  g.add_identity,
+                    g.alpha,          g.beta};
+}
+
+namespace {
 
 // ------------------------------------------------------------- tracing ----
 struct TraceRec {
@@ -172,50 +192,6 @@ void trace_cb(void *vctx, const LaunchInfo &li, int phase) {
                                    ctx->pending, stop});
         ctx->pending = nullptr;
     }
-}
-
-// ------------------------------------------------------------ workspace ----
-// Layout of a stream's workspace (bytes):
-//   [0, 256)          status words (int): 0 = pivot status, 1 = refinement status
-//   [256, 4096)       small doubles: 0..7 refinement norms, 8..15 misc norms
-//   [4096, +8 KiB)    Frobenius-norm partials
-//   then              recursion workspace, leaf scratch, mixed-mode buffers
-constexpr size_t kHdr = 4096 + 8192 + 4096;
-constexpr int kNormSlots = 8;
-
-inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
-
-struct Layout {
-    size_t rec_off, rec_bytes;
-    size_t leaf_off, leaf_bytes;
-    size_t a32_off, x32_off, r_off, xalt_off;
-    size_t total;
-};
-
-Layout layout_for(int64_t n, int64_t leaf, int mode, int64_t ws_elems, int64_t max_leaf) {
-    Layout L{};
-    const size_t es = (mode == SPIN_FP64) ? 8 : 4;
-    size_t off = kHdr;
-    L.rec_off = off;
-    L.rec_bytes = al256((size_t)ws_elems * es);
-    off += L.rec_bytes;
-    L.leaf_off = off;
-    L.leaf_bytes = al256(leaf_scratch_bytes(max_leaf));
-    off += L.leaf_bytes;
-    if (mode != SPIN_FP64) {
-        const size_t nn = (size_t)n * (size_t)n;
-        L.a32_off = off;
-        off += al256(nn * 4);
-        L.x32_off = off;
-        off += al256(nn * 4);
-        L.r_off = off;
-        off += al256(nn * 8);
-        L.xalt_off = off;
-        off += al256(nn * 8);
-    }
-    (void)leaf;
-    L.total = off;
-    return L;
 }
 
 struct Workspace {
@@ -283,15 +259,7 @@ hipError_t run_plan(const Plan &P, const Exec &E) {
         const bool tr = g_trace_on;
         if (op.kind == 0) {
             GemmProb pr[2];
-            for (int q = 0; q < op.count; ++q) {
-                const PGemm &g = op.g[q];
-                const bool use_c = g.beta != 0.0;
-                pr[q] = GemmProb{at(E, g.a),       at(E, g.b),  use_c ? at(E, g.c) : nullptr,
-                                 at(E, g.d),       g.a.ld,      g.b.ld,
-                                 use_c ? g.c.ld : 1, g.d.ld,    (int32_t)g.m,
-                                 (int32_t)g.n,     (int32_t)g.k, g.add_identity,
-                                 g.alpha,          g.beta};
-            }
+            for (int q = 0; q < op.count; ++q) pr[q] = make_prob(E.base, E.es, op.g[q]);
             LaunchInfo li{};
             if (tr) trace_cb(&ctx, li, 0);
             hipError_t e = gemm_launch(pr, op.count, E.dt, E.s, &li);

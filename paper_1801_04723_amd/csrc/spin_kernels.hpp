@@ -26,9 +26,10 @@ struct GemmProb {
     double alpha, beta;
 };
 
-// A launch of up to kMaxGroup independent products (one grid; every
-// workgroup finds its problem from the tile prefix sums).
-constexpr int kMaxGroup = 4;
+// One gemm_launch() call takes up to kMaxBatch independent products; products
+// that share a kernel configuration run in one grid (every workgroup finds
+// its problem from the tile prefix sums).
+constexpr int kMaxBatch = 32;
 
 // Per-launch bookkeeping returned to the scheduler for tracing.
 struct LaunchInfo {
@@ -38,6 +39,8 @@ struct LaunchInfo {
 };
 
 // GEMM family (gemm.hip).  dt selects operand/result type and MFMA flavour.
+// The kernel configuration of each product depends only on that product, so
+// grouping products from different requests does not change any result bit.
 hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s,
                        LaunchInfo *info);
 
@@ -52,6 +55,25 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                        int64_t ldo, int64_t L, int64_t col0, int *status, void *scratch,
                        hipStream_t s, void (*trace_cb)(void *, const LaunchInfo &, int),
                        void *trace_ctx);
+
+// Whole leaves of order <= 128 from independent requests, one workgroup each,
+// in one launch (per leaf size class); each leaf's result is identical to the
+// one leaf_launch() produces for it.
+struct LeafItem {
+    const void *in;
+    int64_t ldi;
+    void *out;
+    int64_t ldo;
+    int64_t L, col0;
+    int *status;
+};
+constexpr int kMaxLeafBatch = 32;
+struct LeafBatch {
+    LeafItem item[kMaxLeafBatch];
+    int32_t count;
+};
+hipError_t leaf_batch_launch(const LeafItem *items, int count, DType dt, hipStream_t s,
+                             LaunchInfo *info);
 
 // Auxiliary kernels (aux.hip).
 // Status words start at INT_MAX ("no event"); kernels lower them atomically.

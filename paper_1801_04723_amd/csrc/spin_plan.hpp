@@ -1,0 +1,74 @@
+// Recursion planner shared by the single-call executor (spin_api.cpp) and
+// the batching server (spin_server.cpp).  Not installed.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "spin_kernels.hpp"
+
+namespace spin {
+
+enum Buf { BUF_A = 0, BUF_X = 1, BUF_WS = 2 };
+
+// A view: buffer id, element offset and leading dimension.
+struct Ref {
+    int buf;
+    int64_t off;
+    int64_t ld;
+};
+
+// One block product of the schedule: D = alpha A B + beta C (+ I).
+struct PGemm {
+    Ref a, b, c, d;
+    int64_t m, n, k;
+    double alpha, beta;
+    int add_identity;
+};
+
+// One step: a group of independent products (kind 0) or a leaf (kind 1).
+struct POp {
+    int kind;
+    int count;
+    int level;
+    PGemm g[2];
+    Ref in, out;
+    int64_t L, col0;
+};
+
+struct Plan {
+    int64_t n = 0, lda = 0, ldx = 0, leaf = 0;
+    std::vector<POp> ops;
+    int64_t ws_elems = 0;
+    int64_t max_leaf = 0;
+    double flops = 0;
+};
+
+// Layout of one inversion's workspace (bytes):
+//   [0, 256)          status words (int): 0 = pivot status, 1 = refinement status
+//   [256, 4096)       small doubles: 0..7 refinement norms, 8..15 misc norms
+//   [4096, +8 KiB)    Frobenius-norm partials
+//   then              recursion workspace, leaf scratch, mixed-mode buffers
+constexpr size_t kHdr = 4096 + 8192 + 4096;
+constexpr int kNormSlots = 8;
+inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t rec_off, rec_bytes;
+    size_t leaf_off, leaf_bytes;
+    size_t a32_off, x32_off, r_off, xalt_off;
+    size_t total;
+};
+Layout layout_for(int64_t n, int64_t leaf, int mode, int64_t ws_elems, int64_t max_leaf);
+
+// The kernel-level product of a scheduled one, for buffers A, X and the
+// workspace at base[0..2] with element size es.
+GemmProb make_prob(char *const base[3], size_t es, const PGemm &g);
+
+// Order of the leading block when an order-m block is split.
+int64_t split_order(int64_t m);
+// Depth-first S-form schedule of Alg. 1 for an order-n matrix.
+Plan make_plan(int64_t n, int64_t lda, int64_t ldx, int64_t leaf);
+
+}  // namespace spin

@@ -154,3 +154,52 @@ def test_schedule_replay_equals_oracle_bitwise(gen, n, leaf):
     ref, info = oracle.strassen_inv(A, leaf)
     assert info == 0
     assert np.array_equal(X, ref)
+
+
+# ------------------------------------------------------- server admission (CPU)
+def _fake(i):
+    return 0x100000000 + i * 0x10000000
+
+
+def test_server_fifo_admission_by_footprint():
+    """FIFO admission: requests start while their workspace fits the pool and a
+    slot is free; a request that does not fit blocks those behind it."""
+    L = S.lib()
+    leaf = 64
+    b256 = S.server_request_bytes(256, leaf, "fp64")
+    b1024 = S.server_request_bytes(1024, leaf, "fp64")
+    assert 0 < b256 < b1024
+    # two small requests fit; the big one only fits once they have left
+    pool = b1024 + b256
+    srv = S.Server(pool, max_active=8, leaf=leaf)
+    h = srv._h
+    for i, n in enumerate([256, 256, 1024, 256]):
+        rc = L.spin_server_submit(h, _fake(2 * i), n, n, _fake(2 * i + 1), n, 0, i)
+        assert rc == 0
+    assert srv.admit() == 2
+    st = srv.stats()
+    assert st == {"queued": 2, "active": 2, "pool_used": 2 * b256}
+    assert srv.admit() == 0  # the 1024 request blocks the 256 behind it
+    srv.close()
+
+
+def test_server_slot_cap_and_validation():
+    L = S.lib()
+    srv = S.Server(1 << 30, max_active=3, leaf=64)
+    h = srv._h
+    for i in range(5):
+        assert L.spin_server_submit(h, _fake(2 * i), 128, 128, _fake(2 * i + 1), 128, 1, i) == 0
+    assert srv.admit() == 3
+    assert srv.stats()["queued"] == 2
+    assert L.spin_server_submit(h, None, 128, 128, _fake(99), 128, 0, 9) == -1
+    assert L.spin_server_submit(h, _fake(90), 0, 128, _fake(91), 128, 0, 9) == -2
+    assert L.spin_server_submit(h, _fake(90), 128, 100, _fake(91), 128, 0, 9) == -3
+    assert L.spin_server_submit(h, _fake(90), 128, 128, _fake(91), 128, 5, 9) == -6
+    # overlap of input and output
+    assert L.spin_server_submit(h, _fake(90), 128, 128, _fake(90) + 8, 128, 0, 9) == -5
+    srv.close()
+    tiny = S.Server(1 << 20, max_active=2, leaf=64)
+    assert L.spin_server_submit(tiny._h, _fake(1), 1024, 1024, _fake(2), 1024, 0, 0) == -10
+    tiny.close()
+    assert L.spin_server_create(0, 4, 64, 2) is None
+    assert L.spin_invert_batch(-1, None, None, None, None, None, None, 64, 2, None, None) == -7

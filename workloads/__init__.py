@@ -197,3 +197,35 @@ def serving_trace(rate: float, duration: float, seed: int = 5,
                     "kappa": kappa, "mixed": mixed, "seed": 5000 + i})
         i += 1
     return out
+
+
+# ------------------------------------------------------------ GPU generators
+def torch_diag_dominant(n: int, seed: int, device="cuda"):
+    """Seeded U(-1, 1) + n I generated on a torch device (column-major view)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    a = torch.rand((n, n), generator=g, dtype=torch.float64, device=device) * 2.0 - 1.0
+    a.diagonal().add_(float(n))
+    return a.t().contiguous().t()
+
+
+def torch_spd_spectrum(n: int, seed: int, kappa: float, device="cuda"):
+    """Seeded Q diag(lam) Q^T on a torch device: Q from the QR factorisation of
+    a Gaussian matrix, lam geometric over [1, kappa]; symmetrised."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    z = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+    q, r = torch.linalg.qr(z)
+    s = torch.sign(torch.diagonal(r))
+    s[s == 0] = 1.0
+    q = q * s[None, :]
+    if n == 1:
+        lam = torch.ones(1, dtype=torch.float64, device=device)
+    else:
+        lam = torch.pow(torch.tensor(float(kappa), dtype=torch.float64, device=device),
+                        torch.arange(n, dtype=torch.float64, device=device) / (n - 1))
+    a = (q * lam[None, :]) @ q.t().contiguous()
+    a = 0.5 * (a + a.t())
+    return a.t().contiguous().t()
