@@ -70,6 +70,15 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
 #define SPIN_FP64 0        /* every product and every leaf in FP64            */
 #define SPIN_MIXED_FP32 1  /* block products in FP32 (FP32 MFMA, FP32 accumulation),
                               FP64 leaves, FP64 Newton refinement              */
+#define SPIN_MIXED_BF16 2  /* block products on BF16 matrix cores: FP32 operands
+                              rounded to BF16 (nearest even), FP32 accumulation;
+                              FP64 leaves and refinement.  Too coarse for
+                              kappa ~ 1e4 (refinement diverges, flagged)       */
+#define SPIN_MIXED_BF16X3 3 /* as SPIN_MIXED_BF16 with each operand split into
+                              hi = bf16(x), lo = bf16(x - hi) and the products
+                              hi*hi + lo*hi + hi*lo accumulated in FP32
+                              (about 16 significant bits per operand); needs
+                              one refinement step more than SPIN_MIXED_FP32   */
 
 /* ---- FP64 inversion ------------------------------------------------------- */
 /* Ainv (n x n, ldx) := A^-1 for A (n x n, lda), FP64 throughout.
@@ -108,7 +117,10 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
  * paper's `multiply` (Sec. 3.3) with its `subtract` (Alg. 2) and the sign of
  * `scalarMul` (Alg. 5) folded into the epilogue.  dtype SPIN_FP64: double
  * operands and result, FP64 MFMA.  dtype SPIN_MIXED_FP32: float operands and
- * result, FP32 MFMA with FP32 accumulation.  C0 may be NULL when beta == 0 and
+ * result, FP32 MFMA with FP32 accumulation.  dtype SPIN_MIXED_BF16 /
+ * SPIN_MIXED_BF16X3: float operands and result, the operands rounded (split)
+ * to BF16 as described for those modes, FP32 accumulation; alpha, beta and
+ * the identity are applied in FP64 before the FP32 store.  C0 may be NULL when beta == 0 and
  * may equal D (each element is read before it is written); A and B must not
  * overlap D.  Asynchronous on `stream`. */
 int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha,
@@ -137,7 +149,7 @@ void spin_release(void);
 
 /* ---- batched inversion and continuous batching ---------------------------- */
 /* Inverts `count` independent matrices (each column-major, its own order n[i]
- * and leading dimensions; mode[i] = SPIN_FP64 or SPIN_MIXED_FP32 with
+ * and leading dimensions; mode[i] = SPIN_FP64 or one of the mixed modes with
  * `ns_steps` refinement steps) with cross-request batching: at each step the
  * block products of all requests run in grouped matrix-core launches and
  * their leaves in one batched leaf launch.  Every request's result is bit for

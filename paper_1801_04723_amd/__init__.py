@@ -25,7 +25,11 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "spin.h")
 
 FP64 = 0
 MIXED_FP32 = 1
-MODES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32}
+MIXED_BF16 = 2
+MIXED_BF16X3 = 3
+MODES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32,
+         "bf16": MIXED_BF16, "mixed_bf16": MIXED_BF16,
+         "bf16x3": MIXED_BF16X3, "mixed_bf16x3": MIXED_BF16X3}
 NS_DIVERGED = -100
 MAX_LEAF = 2048
 
@@ -286,7 +290,7 @@ def gemm_cm(m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc, D, ldd, add_identity=
         if x is None:
             return None
         return x if isinstance(x, int) else x.data_ptr()
-    rc = lib().spin_gemm(int(dtype), m, n, k, float(alpha), ptr(A), lda, ptr(B), ldb, float(beta),
+    rc = lib().spin_gemm(_mode(dtype), m, n, k, float(alpha), ptr(A), lda, ptr(B), ldb, float(beta),
                          ptr(C0), ldc, ptr(D), ldd, 1 if add_identity else 0, _stream(stream))
     if rc != 0:
         raise SpinError(rc, "spin_gemm")

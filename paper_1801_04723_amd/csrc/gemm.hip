@@ -360,10 +360,203 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
     }
 }
 
-// One launch of up to N products that share a kernel configuration.
-template <bool FAST, int BM, int BN, int BK, int WM, int WN, typename T, int N>
-hipError_t launch_group(const GemmProb *probs, int count, hipStream_t s) {
-    GroupArgs<N> g{};
+// ------------------------------------------------------------ BF16 path ---
+// Products of FP32 matrices on the BF16 matrix cores with FP32 accumulation.
+// v_mfma_f32_16x16x32_bf16: lane l supplies row l % 16 of an operand at
+// k = 8*(l/16) .. 8*(l/16) + 7 and receives rows 4*(l/16) + v of the result
+// (operands transposed as above, so the result block is D^T).  Operands are
+// rounded to BF16 (round to nearest even) while they are staged into LDS,
+// k-contiguous per m (A) or n (B) row so that each lane fetches its eight k
+// with one 16-byte read; the 80-byte row pitch spreads the 16 rows a
+// quarter-wave reads over all 64 banks.  X3 splits every operand into
+// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32) and
+// accumulates hi*hi + lo*hi + hi*lo, about 16 significant bits per operand
+// (the lo*lo term, of relative size 2^-16, is dropped).
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+template <int KN>
+struct BfVec {
+    typedef __bf16 type __attribute__((ext_vector_type(KN)));
+};
+
+template <int BM, int BN, int WM, int WN, bool X3, bool VEC, int NG>
+__global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
+    constexpr int BK = 32;
+    constexpr int NT = 256;
+    constexpr int WAVES_M = BM / WM;
+    static_assert(WAVES_M * (BN / WN) == 4, "four waves per workgroup");
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int LDK = BK + 8;           // LDS pitch (elements) of one m or n row
+    constexpr int KPA = BM * BK / NT / 4;  // k per thread in the A slab (4 rows each)
+    constexpr int TPC = NT / BN;           // threads per column of the B slab
+    constexpr int KPB = BK / TPC;          // k per thread in the B slab
+    constexpr int NP = X3 ? 2 : 1;         // hi (and lo) planes
+    static_assert(KPA >= 1 && KPB % 4 == 0, "slab/thread mismatch");
+    typedef typename BfVec<KPA>::type va_t;
+    typedef typename BfVec<KPB>::type vb_t;
+
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][NP][BM * LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NP][BN * LDK];
+
+    const int bid = blockIdx.x;
+    const int pi = group_member(g, bid);
+    const GemmProb P = g.p[pi];
+    const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
+    const int t = bid - tstart;
+    const int tm = t % tiles_m, tn = t / tiles_m;
+    const int M = P.m, N = P.n, K = P.k;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const float *__restrict__ A = static_cast<const float *>(P.A);
+    const float *__restrict__ B = static_cast<const float *>(P.B);
+    const int64_t lda = P.lda, ldb = P.ldb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % WAVES_M) * WM, wn0 = (wave / WAVES_M) * WN;
+
+    // A slab: rows 4*mq .. 4*mq+3, k = kq*KPA .. kq*KPA + KPA-1
+    const int mq = tid % (BM / 4), kq = tid / (BM / 4);
+    const int am = m0 + 4 * mq;
+    // B slab: column bn, k = bk .. bk + KPB-1
+    const int bn = tid / TPC, bk = (tid % TPC) * KPB;
+    const int bcol = n0 + bn;
+
+    float ra[KPA][4], rb[KPB];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < KPA; ++j) {
+            const int k = k0 + kq * KPA + j;
+            if (VEC) {
+                const bool ok = am < M && k < K;
+                const float4 x = *reinterpret_cast<const float4 *>(ok ? A + am + (int64_t)k * lda : A);
+                ra[j][0] = ok ? x.x : 0.f;
+                ra[j][1] = ok ? x.y : 0.f;
+                ra[j][2] = ok ? x.z : 0.f;
+                ra[j][3] = ok ? x.w : 0.f;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bool ok = am + i < M && k < K;
+                    const float x = *(ok ? A + am + i + (int64_t)k * lda : A);
+                    ra[j][i] = ok ? x : 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < KPB / 4; ++h) {
+            const int k = k0 + bk + 4 * h;
+            if (VEC) {
+                const bool ok = bcol < N && k < K;
+                const float4 x = *reinterpret_cast<const float4 *>(ok ? B + k + (int64_t)bcol * ldb : B);
+                rb[4 * h + 0] = ok ? x.x : 0.f;
+                rb[4 * h + 1] = ok ? x.y : 0.f;
+                rb[4 * h + 2] = ok ? x.z : 0.f;
+                rb[4 * h + 3] = ok ? x.w : 0.f;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const bool ok = bcol < N && k + i < K;
+                    const float x = *(ok ? B + k + i + (int64_t)bcol * ldb : B);
+                    rb[4 * h + i] = ok ? x : 0.f;
+                }
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            va_t hi, lo;
+#pragma unroll
+            for (int j = 0; j < KPA; ++j) {
+                const __bf16 h = (__bf16)ra[j][i];
+                hi[j] = h;
+                if (X3) lo[j] = (__bf16)(ra[j][i] - (float)h);
+            }
+            *reinterpret_cast<va_t *>(&As[buf][0][(4 * mq + i) * LDK + kq * KPA]) = hi;
+            if (X3) *reinterpret_cast<va_t *>(&As[buf][NP - 1][(4 * mq + i) * LDK + kq * KPA]) = lo;
+        }
+        vb_t hi, lo;
+#pragma unroll
+        for (int j = 0; j < KPB; ++j) {
+            const __bf16 h = (__bf16)rb[j];
+            hi[j] = h;
+            if (X3) lo[j] = (__bf16)(rb[j] - (float)h);
+        }
+        *reinterpret_cast<vb_t *>(&Bs[buf][0][bn * LDK + bk]) = hi;
+        if (X3) *reinterpret_cast<vb_t *>(&Bs[buf][NP - 1][bn * LDK + bk]) = lo;
+    };
+
+    f4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+
+    const int g4 = lane >> 4, c16 = lane & 15;
+    auto compute = [&](int buf) {
+        bf8_t a[NP][TM], b[NP][TN];
+#pragma unroll
+        for (int pl = 0; pl < NP; ++pl) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                a[pl][i] = *reinterpret_cast<const bf8_t *>(&As[buf][pl][(wm0 + 16 * i + c16) * LDK + 8 * g4]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                b[pl][j] = *reinterpret_cast<const bf8_t *>(&Bs[buf][pl][(wn0 + 16 * j + c16) * LDK + 8 * g4]);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[0][j], a[0][i], acc[i][j], 0, 0, 0);
+                if (X3) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[0][j], a[NP - 1][i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[NP - 1][j], a[0][i], acc[i][j], 0, 0, 0);
+                }
+            }
+    };
+
+    const int KT = (K + BK - 1) / BK;
+    if (KT > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int kt = 0; kt + 1 < KT; ++kt) {
+            gload((kt + 1) * BK);
+            compute(kt & 1);
+            sstore((kt & 1) ^ 1);
+            __syncthreads();
+        }
+        compute((KT - 1) & 1);
+    }
+
+    const float *__restrict__ C0 = static_cast<const float *>(P.C0);
+    float *D = static_cast<float *>(P.D);
+    const double alpha = P.alpha, beta = P.beta;
+    const bool use_c = (beta != 0.0) && (C0 != nullptr);
+    const bool add_i = P.add_identity != 0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int gm = m0 + wm0 + i * 16 + c16;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gn = n0 + wn0 + j * 16 + 4 * g4 + v;
+                if (gm < M && gn < N) {
+                    double val = alpha * (double)acc[i][j][v];
+                    if (use_c) val += beta * (double)C0[gm + (int64_t)gn * P.ldc];
+                    if (add_i && gm == gn) val += 1.0;
+                    D[gm + (int64_t)gn * P.ldd] = (float)val;
+                }
+            }
+        }
+    }
+}
+
+// Tile prefix sums of up to N products for a BM x BN tiling; returns the
+// number of workgroups.
+template <int BM, int BN, int N>
+int make_group(const GemmProb *probs, int count, GroupArgs<N> &g) {
+    g = GroupArgs<N>{};
     g.count = count;
     int total = 0;
     for (int q = 0; q < N; ++q) {
@@ -380,11 +573,28 @@ hipError_t launch_group(const GemmProb *probs, int count, hipStream_t s) {
         }
     }
     g.tile_start[N] = total;
+    return total;
+}
+
+// One launch of up to N products that share a kernel configuration.
+template <bool FAST, int BM, int BN, int BK, int WM, int WN, typename T, int N>
+hipError_t launch_group(const GemmProb *probs, int count, hipStream_t s) {
+    GroupArgs<N> g;
+    const int total = make_group<BM, BN, N>(probs, count, g);
     if (total == 0) return hipSuccess;
     if constexpr (FAST)
         hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
     else
         hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+template <int BM, int BN, int WM, int WN, bool X3, bool VEC, int N>
+hipError_t launch_bf16_group(const GemmProb *probs, int count, hipStream_t s) {
+    GroupArgs<N> g;
+    const int total = make_group<BM, BN, N>(probs, count, g);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL((gemm_bf16<BM, BN, WM, WN, X3, VEC, N>), dim3(total), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -402,15 +612,23 @@ struct Cfg {
     bool operator==(const Cfg &o) const { return tile == o.tile && fast == o.fast; }
 };
 
-Cfg choose_cfg(const GemmProb &p, int es) {
+Cfg choose_cfg(const GemmProb &p, DType dt) {
+    const int es = dt == kF64 ? 8 : 4;
     const int vw = 16 / es;
     const int64_t t128 = (int64_t)((p.m + 127) / 128) * ((p.n + 127) / 128);
     const int64_t t64 = (int64_t)((p.m + 63) / 64) * ((p.n + 63) / 64);
     Cfg c;
     c.tile = (t128 >= 192) ? 128 : (t64 >= 128) ? 64 : 32;
+    const bool aligned =
+        ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.B)) & 15) == 0;
+    if (dt == kBF16 || dt == kBF16X3) {
+        // float4 loads along m (A) and along k (B)
+        c.fast = p.m % 4 == 0 && p.k % 4 == 0 && p.lda % 4 == 0 && p.ldb % 4 == 0 && aligned;
+        return c;
+    }
     const int bk = fast_bk(c.tile, es);
     c.fast = p.k > 0 && p.k % bk == 0 && p.m % vw == 0 && p.lda % vw == 0 && p.ldb % vw == 0 &&
-             ((reinterpret_cast<uintptr_t>(p.A) | reinterpret_cast<uintptr_t>(p.B)) & 15) == 0;
+             aligned;
     return c;
 }
 
@@ -427,20 +645,39 @@ hipError_t launch_cfg(Cfg c, const GemmProb *probs, int count, hipStream_t s) {
                   : launch_group<false, 32, 32, 32, 16, 16, T, N>(probs, count, s);
 }
 
+template <bool X3, int N>
+hipError_t launch_cfg_bf16(Cfg c, const GemmProb *probs, int count, hipStream_t s) {
+    if (c.tile == 128)
+        return c.fast ? launch_bf16_group<128, 128, 64, 64, X3, true, N>(probs, count, s)
+                      : launch_bf16_group<128, 128, 64, 64, X3, false, N>(probs, count, s);
+    if (c.tile == 64)
+        return c.fast ? launch_bf16_group<64, 64, 32, 32, X3, true, N>(probs, count, s)
+                      : launch_bf16_group<64, 64, 32, 32, X3, false, N>(probs, count, s);
+    return c.fast ? launch_bf16_group<32, 32, 16, 16, X3, true, N>(probs, count, s)
+                  : launch_bf16_group<32, 32, 16, 16, X3, false, N>(probs, count, s);
+}
+
 const char *cfg_name(Cfg c, DType dt) {
-    static const char *names[2][3][2] = {
+    static const char *names[4][3][2] = {
         {{"gemm_f64_128x128_edge", "gemm_f64_128x128"}, {"gemm_f64_64x64_edge", "gemm_f64_64x64"},
          {"gemm_f64_32x32_edge", "gemm_f64_32x32"}},
         {{"gemm_f32_128x128_edge", "gemm_f32_128x128"}, {"gemm_f32_64x64_edge", "gemm_f32_64x64"},
-         {"gemm_f32_32x32_edge", "gemm_f32_32x32"}}};
+         {"gemm_f32_32x32_edge", "gemm_f32_32x32"}},
+        {{"gemm_bf16_128x128_edge", "gemm_bf16_128x128"},
+         {"gemm_bf16_64x64_edge", "gemm_bf16_64x64"},
+         {"gemm_bf16_32x32_edge", "gemm_bf16_32x32"}},
+        {{"gemm_bf16x3_128x128_edge", "gemm_bf16x3_128x128"},
+         {"gemm_bf16x3_64x64_edge", "gemm_bf16x3_64x64"},
+         {"gemm_bf16x3_32x32_edge", "gemm_bf16x3_32x32"}}};
     const int ti = c.tile == 128 ? 0 : c.tile == 64 ? 1 : 2;
-    return names[dt == kF64 ? 0 : 1][ti][c.fast ? 1 : 0];
+    return names[(int)dt][ti][c.fast ? 1 : 0];
 }
 
 }  // namespace
 
 hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s, LaunchInfo *info) {
     if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if (dt != kF64 && dt != kF32 && dt != kBF16 && dt != kBF16X3) return hipErrorInvalidValue;
     const int esz = (dt == kF64) ? 8 : 4;
     const double es = esz;
     // Products with an empty reduction still need their epilogue; drop only
@@ -453,7 +690,7 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
     for (int q = 0; q < count; ++q) {
         if (probs[q].m <= 0 || probs[q].n <= 0) continue;
         part[n_live] = probs[q];
-        cfgs[n_live] = choose_cfg(probs[q], esz);
+        cfgs[n_live] = choose_cfg(probs[q], dt);
         done[n_live] = false;
         ++n_live;
         const double m = probs[q].m, n = probs[q].n, k = probs[q].k;
@@ -475,9 +712,15 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
         if (dt == kF64)
             e = (ng <= 2) ? launch_cfg<double, 2>(cfgs[q], grp, ng, s)
                           : launch_cfg<double, kMaxBatch>(cfgs[q], grp, ng, s);
-        else
+        else if (dt == kF32)
             e = (ng <= 2) ? launch_cfg<float, 2>(cfgs[q], grp, ng, s)
                           : launch_cfg<float, kMaxBatch>(cfgs[q], grp, ng, s);
+        else if (dt == kBF16)
+            e = (ng <= 2) ? launch_cfg_bf16<false, 2>(cfgs[q], grp, ng, s)
+                          : launch_cfg_bf16<false, kMaxBatch>(cfgs[q], grp, ng, s);
+        else
+            e = (ng <= 2) ? launch_cfg_bf16<true, 2>(cfgs[q], grp, ng, s)
+                          : launch_cfg_bf16<true, kMaxBatch>(cfgs[q], grp, ng, s);
     }
     if (info) {
         info->name = name;

@@ -244,9 +244,10 @@ struct Exec {
     hipStream_t s;
     char *base[3];
     size_t es;
-    DType dt;
+    DType dt;  // storage type of the plan's operands and leaves
     int *status;
     void *leaf_scratch;
+    DType gdt = kF64;  // product flavour of the plan's products
 };
 
 inline void *at(const Exec &E, const Ref &r) {
@@ -262,7 +263,7 @@ hipError_t run_plan(const Plan &P, const Exec &E) {
             for (int q = 0; q < op.count; ++q) pr[q] = make_prob(E.base, E.es, op.g[q]);
             LaunchInfo li{};
             if (tr) trace_cb(&ctx, li, 0);
-            hipError_t e = gemm_launch(pr, op.count, E.dt, E.s, &li);
+            hipError_t e = gemm_launch(pr, op.count, E.gdt, E.s, &li);
             if (tr) trace_cb(&ctx, li, 1);
             if (e != hipSuccess) return e;
         } else {
@@ -372,7 +373,7 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
                       spin_stream_t stream) {
     int rc = validate(A, n, lda, Ainv, ldx, leaf);
     if (rc) return rc;
-    if (mode != SPIN_MIXED_FP32 || ns_steps < 0 || ns_steps > kNormSlots) return SPIN_E_MODE;
+    if (!is_mixed_mode(mode) || ns_steps < 0 || ns_steps > kNormSlots) return SPIN_E_MODE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(g_mu);
     Plan P = make_plan(n, n, n, leaf);
@@ -400,7 +401,7 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
         e = cast_f64_to_f32(A, lda, A32, n, n, n, qs);
         if (e != hipSuccess) return e;
         Exec E{qs, {(char *)A32, (char *)X32, base + L.rec_off}, 4, kF32, status,
-               base + L.leaf_off};
+               base + L.leaf_off, mixed_product_type(mode)};
         e = run_plan(P, E);
         if (e != hipSuccess) return e;
         e = cast_f32_to_f64(X32, n, buf0, ld0, n, n, qs);
@@ -485,7 +486,7 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
 int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha, const void *A,
               int64_t lda, const void *B, int64_t ldb, double beta, const void *C0, int64_t ldc,
               void *D, int64_t ldd, int add_identity, spin_stream_t stream) {
-    if (dtype != SPIN_FP64 && dtype != SPIN_MIXED_FP32) return SPIN_E_MODE;
+    if (!is_mode(dtype)) return SPIN_E_MODE;
     if (m < 0 || n < 0 || k < 0 || m > INT32_MAX || n > INT32_MAX || k > INT32_MAX)
         return SPIN_E_N;
     if (!D || (k > 0 && (!A || !B)) || (beta != 0.0 && !C0)) return SPIN_E_NULL;
@@ -500,7 +501,7 @@ int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha, const vo
     TraceCtx ctx{s, -1, nullptr};
     LaunchInfo li{};
     if (g_trace_on) trace_cb(&ctx, li, 0);
-    hipError_t e = gemm_launch(&pr, 1, dtype == SPIN_FP64 ? kF64 : kF32, s, &li);
+    hipError_t e = gemm_launch(&pr, 1, dtype == SPIN_FP64 ? kF64 : mixed_product_type(dtype), s, &li);
     if (g_trace_on) trace_cb(&ctx, li, 1);
     return e == hipSuccess ? SPIN_OK : hip_fail(e);
 }
@@ -549,7 +550,7 @@ int spin_residual(const double *A, int64_t n, int64_t lda, const double *X, int6
 
 size_t spin_workspace_bytes(int64_t n, int64_t leaf, int mode) {
     if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > SPIN_MAX_LEAF) return 0;
-    if (mode != SPIN_FP64 && mode != SPIN_MIXED_FP32) return 0;
+    if (!is_mode(mode)) return 0;
     Plan P = make_plan(n, n, n, leaf);
     return layout_for(n, leaf, mode, P.ws_elems, P.max_leaf).total;
 }

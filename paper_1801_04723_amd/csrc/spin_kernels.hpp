@@ -9,7 +9,13 @@
 
 namespace spin {
 
-enum DType : int32_t { kF64 = 0, kF32 = 1 };
+// Element types.  kBF16 and kBF16X3 are product flavours on FP32 storage:
+// the operands are rounded to BF16 (X3: split into two BF16 terms) on their
+// way into the matrix cores, and accumulation and results stay FP32.
+enum DType : int32_t { kF64 = 0, kF32 = 1, kBF16 = 2, kBF16X3 = 3 };
+
+// Storage type of a product flavour.
+inline DType storage_type(DType d) { return d == kF64 ? kF64 : kF32; }
 
 // Largest leaf order the leaf kernels accept.
 constexpr int kLeafMaxOrder = 2048;

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <vector>
 
+#include "spin.h"
 #include "spin_kernels.hpp"
 
 namespace spin {
@@ -53,6 +54,17 @@ struct Plan {
 constexpr size_t kHdr = 4096 + 8192 + 4096;
 constexpr int kNormSlots = 8;
 inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Precision modes of the C ABI.
+inline bool is_mixed_mode(int mode) {
+    return mode == SPIN_MIXED_FP32 || mode == SPIN_MIXED_BF16 || mode == SPIN_MIXED_BF16X3;
+}
+inline bool is_mode(int mode) { return mode == SPIN_FP64 || is_mixed_mode(mode); }
+// Product flavour of the block products of a mode (operands stay FP32 in
+// every mixed mode; leaves, residual and refinement stay FP64).
+inline DType mixed_product_type(int mode) {
+    return mode == SPIN_MIXED_BF16 ? kBF16 : mode == SPIN_MIXED_BF16X3 ? kBF16X3 : kF32;
+}
 
 struct Layout {
     size_t rec_off, rec_bytes;

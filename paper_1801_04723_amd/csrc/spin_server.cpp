@@ -122,12 +122,13 @@ Step aux_step(int op) {
     return s;
 }
 
-void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType dt, int *status,
+// gdt: product flavour of the plan's products; leaves use its storage type.
+void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, int *status,
                     void *leaf_scratch, std::vector<Step> &out) {
     for (const POp &op : P.ops) {
         Step st;
         std::memset(&st, 0, sizeof(st));
-        st.dt = dt;
+        st.dt = op.kind == 0 ? gdt : storage_type(gdt);
         if (op.kind == 0) {
             st.kind = STEP_GEMM;
             st.nprob = op.count;
@@ -175,7 +176,7 @@ void build_steps(Request &r, int64_t leaf, int ns_steps) {
     c.src = r.A, c.lds = r.lda, c.dst = A32, c.ldd = n, c.m = n, c.n = n;
     r.steps.push_back(c);
     char *const base[3] = {(char *)A32, (char *)X32, w + L.rec_off};
-    add_plan_steps(P, base, 4, kF32, status, w + L.leaf_off, r.steps);
+    add_plan_steps(P, base, 4, mixed_product_type(r.mode), status, w + L.leaf_off, r.steps);
     Step wd = aux_step(AUX_WIDEN);
     wd.src = X32, wd.lds = n, wd.dst = buf0, wd.ldd = ld0, wd.m = n, wd.n = n;
     r.steps.push_back(wd);
@@ -301,7 +302,7 @@ int spin_server_submit(spin_server *s, const double *A, int64_t n, int64_t lda, 
     if (!s || !A || !Ainv) return SPIN_E_NULL;
     if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
     if (lda < n || ldx < n) return SPIN_E_LD;
-    if (mode != SPIN_FP64 && mode != SPIN_MIXED_FP32) return SPIN_E_MODE;
+    if (!is_mode(mode)) return SPIN_E_MODE;
     const char *a0 = reinterpret_cast<const char *>(A), *x0 = reinterpret_cast<const char *>(Ainv);
     const char *a1 = a0 + ((size_t)(n - 1) * lda + n) * 8, *x1 = x0 + ((size_t)(n - 1) * ldx + n) * 8;
     if (a0 < x1 && x0 < a1) return SPIN_E_ALIAS;
@@ -337,8 +338,8 @@ int spin_server_tick(spin_server *s, spin_stream_t stream) {
         for (Request *r : s->active) r->ws = s->pool + r->ws_off;
     }
     admit(s);
-    std::vector<GemmProb> g[2];
-    std::vector<LeafItem> lf[2];
+    std::vector<GemmProb> g[4];  // by product flavour (DType)
+    std::vector<LeafItem> lf[2];  // by storage type
     std::vector<Request *> finished;
     hipError_t e = hipSuccess;
     for (Request *r : s->active) {
@@ -353,7 +354,7 @@ int spin_server_tick(spin_server *s, spin_stream_t stream) {
                 continue;
             }
             if (stp.kind == STEP_GEMM) {
-                for (int q = 0; q < stp.nprob; ++q) g[stp.dt == kF64 ? 0 : 1].push_back(stp.prob[q]);
+                for (int q = 0; q < stp.nprob; ++q) g[(int)stp.dt].push_back(stp.prob[q]);
             } else if (stp.leaf.L <= 128) {
                 lf[stp.dt == kF64 ? 0 : 1].push_back(stp.leaf);
             } else {
@@ -366,11 +367,12 @@ int spin_server_tick(spin_server *s, spin_stream_t stream) {
         }
         if (r->next >= r->steps.size()) finished.push_back(r);
     }
-    for (int d = 0; d < 2 && e == hipSuccess; ++d) {
+    for (int d = 0; d < 4 && e == hipSuccess; ++d) {
         for (size_t i = 0; i < g[d].size() && e == hipSuccess; i += kMaxBatch) {
             const int cnt = (int)std::min<size_t>(kMaxBatch, g[d].size() - i);
-            e = gemm_launch(g[d].data() + i, cnt, d == 0 ? kF64 : kF32, st, nullptr);
+            e = gemm_launch(g[d].data() + i, cnt, (DType)d, st, nullptr);
         }
+        if (d >= 2) continue;
         for (size_t i = 0; i < lf[d].size() && e == hipSuccess; i += kMaxLeafBatch) {
             const int cnt = (int)std::min<size_t>(kMaxLeafBatch, lf[d].size() - i);
             e = leaf_batch_launch(lf[d].data() + i, cnt, d == 0 ? kF64 : kF32, st, nullptr);
@@ -421,7 +423,7 @@ int spin_server_stats(spin_server *s, int64_t *queued, int64_t *active, size_t *
 
 size_t spin_server_request_bytes(int64_t n, int64_t leaf, int mode) {
     if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > SPIN_MAX_LEAF) return 0;
-    if (mode != SPIN_FP64 && mode != SPIN_MIXED_FP32) return 0;
+    if (!is_mode(mode)) return 0;
     return al256(request_bytes(n, leaf, mode));
 }
 
@@ -436,7 +438,7 @@ int spin_invert_batch(int64_t count, const double *const *A, const int64_t *n, c
     size_t total = 0;
     for (int64_t i = 0; i < count; ++i) {
         if (n[i] < 1 || n[i] > SPIN_MAX_N) return SPIN_E_N;
-        if (mode[i] != SPIN_FP64 && mode[i] != SPIN_MIXED_FP32) return SPIN_E_MODE;
+        if (!is_mode(mode[i])) return SPIN_E_MODE;
         total += al256(request_bytes(n[i], leaf, mode[i]));
     }
     spin_server *s = spin_server_create(total, (int)count, leaf, ns_steps);

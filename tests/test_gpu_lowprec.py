@@ -1,0 +1,154 @@
+"""GPU parity of the BF16 product flavours and of the BF16 mixed modes.
+
+Products: the GPU result (operands rounded or split to BF16 in the kernel,
+FP32 accumulation) against the oracle's exact-operand product of the same
+FP32 inputs (oracle/lowprec.py), element by element, within the FP32
+accumulation bound (k + 2) u32 (|op(A)| |op(B)| + |C|).  A BF16 rounding that
+differed from round-to-nearest-even anywhere would miss by about 2^-9 of a
+term, far outside that bound.
+
+Inversions: the mixed modes refined by FP64 Newton steps reach the FP64
+residual target where the survey-time numerics say they should (bf16x3 on
+SPD kappa = 1e4; plain BF16 on diagonally dominant input), and plain BF16 on
+SPD kappa = 1e4 is reported as diverged.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import lowprec as LP
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev32(torch, a):
+    a = np.asarray(a, dtype=np.float32)
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().t()
+
+
+def _dev64(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64).T)).cuda().t()
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+# m % 4, k % 4 and the leading dimensions decide between the vector and the
+# guarded kernel; the tile count decides between 128, 64 and 32 tiles.
+SHAPES = [(64, 64, 64), (200, 136, 300), (130, 70, 45), (33, 17, 5), (1, 1, 1),
+          (512, 512, 512), (2048, 1536, 96), (2050, 1540, 99)]
+
+
+@pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("m,n,k", SHAPES)
+def test_gemm_lowprec_parity(torch_cuda, mode, m, n, k):
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    g = np.random.default_rng(m * 7 + n * 3 + k)
+    A = g.standard_normal((m, k)).astype(np.float32)
+    B = g.standard_normal((k, n)).astype(np.float32)
+    C = g.standard_normal((m, n)).astype(np.float32)
+    dA, dB, dC = _dev32(torch, A), _dev32(torch, B), _dev32(torch, C)
+    dD = torch.zeros_like(dC)
+    S.gemm_cm(m, n, k, -1.0, dA, m, dB, k, 1.0, dC, m, dD, m, False, mode)
+    torch.cuda.synchronize()
+    ref = C.astype(np.float64) - LP.gemm_lowprec(A, B, mode)
+    bound = 2 * (k + 2) * U32 * (LP.abs_product(A, B, mode) + np.abs(C))
+    err = np.abs(_host(dD).astype(np.float64) - ref)
+    assert np.all(err <= bound), (float(err.max()), float(bound.min()))
+
+
+@pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
+def test_gemm_lowprec_identity_epilogue_and_ld(torch_cuda, mode):
+    """R = I - A B with padded leading dimensions (the residual form)."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    m, k, lda, ldb, ldd = 96, 80, 100, 84, 104
+    g = np.random.default_rng(5)
+    A = g.uniform(-1, 1, (lda, k)).astype(np.float32)
+    B = g.uniform(-1, 1, (ldb, m)).astype(np.float32)
+    dA, dB = _dev32(torch, A), _dev32(torch, B)
+    dD = _dev32(torch, np.full((ldd, m), 7.0, np.float32))
+    S.gemm_cm(m, m, k, -1.0, dA, lda, dB, ldb, 0.0, None, ldd, dD, ldd, True, mode)
+    torch.cuda.synchronize()
+    a, b = A[:m, :], B[:k, :]
+    ref = np.eye(m) - LP.gemm_lowprec(a, b, mode)
+    bound = 2 * (k + 2) * U32 * (LP.abs_product(a, b, mode) + 1.0)
+    D = _host(dD)
+    assert np.all(np.abs(D[:m, :].astype(np.float64) - ref) <= bound)
+    assert np.all(D[m:, :] == 7.0)  # rows beyond m untouched
+
+
+def test_bf16_is_coarser_than_bf16x3_is_coarser_than_fp32(torch_cuda):
+    """The three flavours differ from the FP64 product in the expected order."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    n = 256
+    g = np.random.default_rng(9)
+    A = g.standard_normal((n, n)).astype(np.float32)
+    B = g.standard_normal((n, n)).astype(np.float32)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    errs = {}
+    for mode in ("fp32", "bf16x3", "bf16"):
+        dD = _dev32(torch, np.zeros((n, n), np.float32))
+        S.gemm_cm(n, n, n, 1.0, _dev32(torch, A), n, _dev32(torch, B), n, 0.0, None, n, dD, n,
+                  False, mode)
+        torch.cuda.synchronize()
+        errs[mode] = float(np.abs(_host(dD) - ref).max())
+    assert errs["fp32"] < errs["bf16x3"] < errs["bf16"] / 30, errs
+
+
+# ------------------------------------------------------------- inversions
+@pytest.mark.parametrize("n,leaf", [(512, 128), (1024, 256)])
+def test_mixed_bf16x3_spd_refined_to_fp64(torch_cuda, n, leaf):
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    A = W.spd_spectrum(n, seed=n + 1, kappa=1e4)
+    dA = _dev64(torch, A)
+    X, rep = S.invert_mixed(dA, leaf=leaf, mode="bf16x3", ns_steps=3, report=True)
+    X = _host(X)
+    assert rep["status"] == 0, rep
+    assert rep["rho_before"] <= 1e-3, rep
+    assert rep["rho_after"] <= 1e-12, rep
+    assert oracle.residual(A, X) <= 1e-12
+    ref, _ = oracle.strassen_inv(A, leaf)
+    kap = np.linalg.cond(A)
+    assert np.linalg.norm(X - ref) / np.linalg.norm(ref) <= max(1e-13, 100 * kap * U)
+
+
+def test_mixed_bf16_diag_dominant_refined(torch_cuda):
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    n = 512
+    A = W.diag_dominant(n, seed=21)
+    dA = _dev64(torch, A)
+    X, rep = S.invert_mixed(dA, leaf=128, mode="bf16", ns_steps=3, report=True)
+    assert rep["status"] == 0, rep
+    assert rep["rho_before"] <= 1e-3, rep
+    assert rep["rho_after"] <= 1e-12, rep
+    assert oracle.residual(A, _host(X)) <= 1e-12
+
+
+def test_mixed_bf16_spd_kappa_1e4_flagged_diverged(torch_cuda):
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    n = 512
+    A = W.spd_spectrum(n, seed=22, kappa=1e4)
+    dA = _dev64(torch, A)
+    _, rep = S.invert_mixed(dA, leaf=128, mode="bf16", ns_steps=3, report=True)
+    assert rep["status"] == S.NS_DIVERGED, rep
+    assert not (rep["rho_after"] <= 1e-12)
+    assert S.info() == S.NS_DIVERGED

@@ -59,6 +59,21 @@ def test_argument_validation_codes():
     assert L.spin_gemm(0, 4, 4, 4, 1.0, A, 4, A, 4, 1.0, None, 4, X, 4, 0, s) == -1
     assert L.spin_workspace_bytes(0, 4, 0) == 0
     assert L.spin_workspace_bytes(64, 4, 9) == 0
+    assert L.spin_invert_mixed(A, 8, 8, X, 8, 2, 0, 2, None, s) == -6  # FP64 is not mixed
+    assert L.spin_invert_mixed(A, 8, 8, X, 8, 2, 4, 2, None, s) == -6
+    assert L.spin_gemm(4, 4, 4, 4, 1.0, A, 4, A, 4, 0.0, None, 4, X, 4, 0, s) == -6
+
+
+def test_mixed_modes_share_one_layout():
+    """The BF16 modes keep FP32 working copies: same workspace as FP32 mode."""
+    for n, leaf in ((64, 16), (1000, 128), (4096, 256)):
+        b1 = S.workspace_bytes(n, leaf, S.MIXED_FP32)
+        assert b1 > S.workspace_bytes(n, leaf, S.FP64) > 0
+        assert S.workspace_bytes(n, leaf, S.MIXED_BF16) == b1
+        assert S.workspace_bytes(n, leaf, S.MIXED_BF16X3) == b1
+        assert S.server_request_bytes(n, leaf, S.MIXED_BF16X3) == S.server_request_bytes(
+            n, leaf, S.MIXED_FP32)
+    assert S.MODES["bf16"] == S.MIXED_BF16 and S.MODES["bf16x3"] == S.MIXED_BF16X3
 
 
 def _levels(n, leaf):
