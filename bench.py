@@ -51,6 +51,10 @@ def parse():
     p.add_argument("--serve-seconds", type=float, default=10.0,
                    help="length of the open-loop serving run (0 disables it)")
     p.add_argument("--serve-rate", type=float, default=200.0, help="serving arrival rate, req/s")
+    p.add_argument("--mixed-n", type=int, default=16384,
+                   help="order of the mixed-precision vs FP64 comparison (0 disables it)")
+    p.add_argument("--mixed-leaf", type=int, default=256)
+    p.add_argument("--mixed-reps", type=int, default=2)
     p.add_argument("--calib-copy", action="store_true",
                    help="run one 512 MiB device-to-device copy first (HBM counter calibration)")
     return p.parse_args()
@@ -109,6 +113,58 @@ def serving(rate: float, seconds: float):
     st["workload"] = (f"Poisson {rate:g} req/s for {seconds:g} s, n log-uniform 64..4096 (x64), "
                       "50% diag-dominant / 50% SPD, 70% mixed FP32+2 Newton / 30% FP64, leaf 128")
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+
+
+def mixed_vs_fp64(n: int, leaf: int, reps: int):
+    """Mixed-precision inversions against the FP64 one on the same matrix and
+    leaf: SPD A = Q diag(lam) Q^T, Q from the QR factorisation of a seeded
+    Gaussian matrix (generated on the GPU), lam geometric over [1, 1e4].
+    Each mode: rho before and after refinement (from the library's report),
+    status, and the mean time of `reps` asynchronous calls after one warm-up."""
+    import torch
+
+    import paper_1801_04723_amd as spin
+    import workloads as W
+    t0 = time.perf_counter()
+    dA = W.torch_spd_spectrum(n, seed=4, kappa=1e4, device="cuda")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    dX = torch.empty_like(dA)
+    runs = [("fp64", 0), ("fp32", 2), ("bf16x3", 3), ("bf16", 2)]
+    out = {"workload": f"spd_spectrum (Q diag(lam) Q^T, kappa 1e4) n={n} generated on the GPU "
+                       f"(seed 4, {gen_s:.1f} s), leaf {leaf}",
+           "n": n, "leaf": leaf, "modes": {}}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for mode, steps in runs:
+        if mode == "fp64":
+            call = lambda: spin.invert(dA, leaf=leaf, out=dX)  # noqa: E731
+        else:
+            call = lambda: spin.invert_mixed(dA, leaf=leaf, mode=mode, ns_steps=steps,  # noqa: E731
+                                             out=dX)
+        call()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rec = {"ms": round(ms, 2), "ns_steps": steps, "tflops_2n3": round(2.0 * n ** 3 / ms / 1e9, 2)}
+        if mode == "fp64":
+            rec["rho"] = spin.residual(dA, dX)
+            rec["status"] = spin.info()
+        else:
+            _, rep = spin.invert_mixed(dA, leaf=leaf, mode=mode, ns_steps=steps, out=dX, report=True)
+            rec.update(rho_before=rep["rho_before"], rho_after=rep["rho_after"],
+                       r_fro=[float(v) for v in rep["r_fro"][:steps]], status=rep["status"])
+        out["modes"][mode] = rec
+    f = out["modes"]["fp64"]["ms"]
+    for mode, _ in runs[1:]:
+        out["modes"][mode]["time_vs_fp64"] = round(out["modes"][mode]["ms"] / f, 3)
+    del dA, dX
+    spin.release()
+    torch.cuda.empty_cache()
+    return out
 
 
 def measured_traffic(kernel: str):
@@ -252,6 +308,11 @@ def main():
         out["roofline"] = None
     if args.serve_seconds > 0:
         out["serving"] = serving(args.serve_rate, args.serve_seconds)
+    if args.mixed_n > 0:
+        del dA, dX
+        spin.release()
+        torch.cuda.empty_cache()
+        out["mixed_precision"] = mixed_vs_fp64(args.mixed_n, args.mixed_leaf, args.mixed_reps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.kind, leaf, seed, args.cpu_budget)
     print(json.dumps(out), flush=True)

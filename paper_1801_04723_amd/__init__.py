@@ -265,8 +265,9 @@ def invert(a, leaf: int, out=None, stream=None):
 
 def invert_mixed(a, leaf: int, mode="fp32", ns_steps: int = 2, out=None, report: bool = False,
                  stream=None):
-    """A^-1 with FP32 block products, FP64 leaves and `ns_steps` FP64 Newton
-    steps.  With report=True the call waits and returns (X, report dict)."""
+    """A^-1 with the block products in `mode` ("fp32", "bf16", "bf16x3"),
+    FP64 leaves and `ns_steps` FP64 Newton steps.  With report=True the call
+    waits and returns (X, report dict)."""
     _check_square(a)
     lda, order = _layout(a)
     if out is None:
