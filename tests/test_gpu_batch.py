@@ -31,11 +31,12 @@ def _dev(torch, a):
 def _solo(S, a, mode, leaf, ns_steps):
     if mode == "fp64":
         return S.invert(a, leaf=leaf)
-    return S.invert_mixed(a, leaf=leaf, ns_steps=ns_steps)
+    return S.invert_mixed(a, leaf=leaf, mode=mode, ns_steps=ns_steps)
 
 
 REQS = [(256, "dd", "fp64"), (320, "spd", "fp32"), (64, "dd", "fp64"), (512, "spdk", "fp32"),
-        (130, "dd", "fp64"), (1024, "spd", "fp64"), (192, "spdk", "fp32"), (40, "dd", "fp32")]
+        (130, "dd", "fp64"), (1024, "spd", "fp64"), (192, "spdk", "fp32"), (40, "dd", "fp32"),
+        (384, "dd", "bf16x3"), (200, "dd", "bf16")]
 
 
 def _mat(n, kind, seed):
