@@ -248,41 +248,39 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
     const int wm0 = (wave % WAVES_M) * WM, wn0 = (wave / WAVES_M) * WN;
 
     const T *pa[AV];
-    bool am[AV];
     int sa[AV];
 #pragma unroll
     for (int i = 0; i < AV; ++i) {
         const int v = tid + NT * i, r = (v % (BM / VW)) * VW, c = v / (BM / VW);
-        am[i] = m0 + r < M;
-        const int row = am[i] ? m0 + r : M - VW;
+        const int row = m0 + r < M ? m0 + r : M - VW;
         pa[i] = static_cast<const T *>(P.A) + row + (int64_t)c * lda;
         sa[i] = c * A_LD + r;
     }
     const T *pb[BV];
-    bool bm[BV];
     int sb[BV];
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
         const int v = tid + NT * i, k = (v % (BK / VW)) * VW, n = v / (BK / VW);
-        bm[i] = n0 + n < N;
-        const int col = bm[i] ? n0 + n : N - 1;
+        const int col = n0 + n < N ? n0 + n : N - 1;
         pb[i] = static_cast<const T *>(P.B) + k + (int64_t)col * ldb;
         sb[i] = n * B_LD + k;
     }
     const int64_t astep = (int64_t)BK * lda;
 
     vec_t ra[AV], rb[BV];
+    // Rows of A beyond M and columns of B beyond N are loaded from clamped
+    // (valid) addresses and not zeroed: they only reach accumulator rows and
+    // columns that the epilogue discards, so the loaded values are consumed
+    // by the LDS stores alone and the compute phase never waits on them.
     auto gload = [&]() {
 #pragma unroll
         for (int i = 0; i < AV; ++i) {
-            const vec_t x = *reinterpret_cast<const vec_t *>(pa[i]);
-            ra[i] = am[i] ? x : vec_t(0);
+            ra[i] = *reinterpret_cast<const vec_t *>(pa[i]);
             pa[i] += astep;
         }
 #pragma unroll
         for (int i = 0; i < BV; ++i) {
-            const vec_t x = *reinterpret_cast<const vec_t *>(pb[i]);
-            rb[i] = bm[i] ? x : vec_t(0);
+            rb[i] = *reinterpret_cast<const vec_t *>(pb[i]);
             pb[i] += BK;
         }
     };
