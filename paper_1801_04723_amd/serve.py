@@ -60,20 +60,30 @@ def percentile(xs, p):
 
 
 def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 << 30,
-              max_active: int = 64, max_ticks_in_flight: int = 64, pool: MatrixPool | None = None):
+              max_active: int = 64, max_ticks_in_flight: int = 64, pool: MatrixPool | None = None,
+              split_n: int | None = None):
     """Serves `trace` (list of dicts with t, n, kind, kappa, mixed) and returns
-    latency / throughput statistics."""
+    latency / throughput statistics.
+
+    With split_n set, requests of order >= split_n go to a second server on a
+    second stream (a quarter of the pool stays with the small-order lane), so
+    the long step sequences of large requests and the many short steps of
+    small ones run side by side instead of taking turns in one stream; each
+    request's result is the same either way."""
     import torch
     pool = pool or MatrixPool()
     # materialise the inputs before the clock starts
     for r in trace:
         pool.get(r["n"], r["kind"], r["kappa"])
     torch.cuda.synchronize()
-    srv = Server(pool_bytes, max_active, leaf, ns_steps)
-    stream = torch.cuda.current_stream()
+    if split_n is None:
+        lanes = [(Server(pool_bytes, max_active, leaf, ns_steps), torch.cuda.current_stream())]
+    else:
+        lanes = [(Server(pool_bytes // 4, max_active, leaf, ns_steps), torch.cuda.Stream()),
+                 (Server(pool_bytes - pool_bytes // 4, max_active, leaf, ns_steps), torch.cuda.Stream())]
+    inflight = [collections.deque() for _ in lanes]
     lat, flops, statuses = [], 0.0, collections.Counter()
     outs = {}
-    inflight = collections.deque()
     nxt = 0
     done = 0
     t0 = time.perf_counter()
@@ -83,28 +93,34 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
             r = trace[nxt]
             a = pool.get(r["n"], r["kind"], r["kappa"])
             x = torch.empty_like(a)
-            srv.submit(a, x, MIXED_FP32 if r["mixed"] else FP64, tag=nxt)
+            lane = 0 if split_n is None or r["n"] < split_n else 1
+            lanes[lane][0].submit(a, x, MIXED_FP32 if r["mixed"] else FP64, tag=nxt)
             outs[nxt] = x
             nxt += 1
-        st = srv.stats()
-        if st["active"] or st["queued"]:
-            srv.tick(stream)
-            ev = torch.cuda.Event()
-            ev.record(stream)
-            inflight.append(ev)
-            while len(inflight) > max_ticks_in_flight:
-                inflight.popleft().synchronize()
-        elif nxt < len(trace):
+        busy = False
+        for (srv, stream), q in zip(lanes, inflight):
+            st = srv.stats()
+            if st["active"] or st["queued"]:
+                busy = True
+                srv.tick(stream)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                q.append(ev)
+                while len(q) > max_ticks_in_flight:
+                    q.popleft().synchronize()
+        if not busy and nxt < len(trace):
             time.sleep(min(1e-3, max(0.0, trace[nxt]["t"] - now)))
-        for tag, info in srv.poll():
-            t_done = time.perf_counter() - t0
-            lat.append(t_done - trace[tag]["t"])
-            flops += 2.0 * trace[tag]["n"] ** 3
-            statuses[info] += 1
-            outs.pop(tag, None)
-            done += 1
+        for srv, _ in lanes:
+            for tag, info in srv.poll():
+                t_done = time.perf_counter() - t0
+                lat.append(t_done - trace[tag]["t"])
+                flops += 2.0 * trace[tag]["n"] ** 3
+                statuses[info] += 1
+                outs.pop(tag, None)
+                done += 1
     makespan = time.perf_counter() - t0
-    srv.close()
+    for srv, _ in lanes:
+        srv.close()
     return {
         "requests": len(trace),
         "p50_ms": 1e3 * percentile(lat, 50),
@@ -118,4 +134,6 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
         "leaf": leaf,
         "ns_steps": ns_steps,
         "max_active": max_active,
+        "lanes": len(lanes),
+        "split_n": split_n,
     }
