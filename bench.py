@@ -221,6 +221,18 @@ def roofline_from_trace(recs, n_steps: int):
     }, breakdown
 
 
+def finite_json(x):
+    """The output with every NaN or infinity replaced by None (strict JSON)."""
+    import math
+    if isinstance(x, float):
+        return x if math.isfinite(x) else None
+    if isinstance(x, dict):
+        return {k: finite_json(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [finite_json(v) for v in x]
+    return x
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -318,7 +330,7 @@ def main():
         out["mixed_precision"] = mixed_vs_fp64(args.mixed_n, args.mixed_leaf, args.mixed_reps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.kind, leaf, seed, args.cpu_budget)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(finite_json(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
