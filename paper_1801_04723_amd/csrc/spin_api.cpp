@@ -204,6 +204,9 @@ std::map<std::tuple<int, int64_t, int64_t, int64_t, int64_t, const void *, void 
          hipGraphExec_t>
     g_graphs;
 hipStream_t g_capture = nullptr;
+// Largest number of cached graphs (one per mode, shape, buffer set and stream
+// workspace) before the cache is emptied.
+constexpr size_t kMaxGraphs = 64;
 
 void drop_graphs_for(void *base) {
     for (auto it = g_graphs.begin(); it != g_graphs.end();) {
@@ -310,6 +313,14 @@ int run_maybe_graph(const std::tuple<int, int64_t, int64_t, int64_t, int64_t, co
         return e == hipSuccess ? SPIN_OK : hip_fail(e);
     }
     auto it = g_graphs.find(key);
+    if (it == g_graphs.end() && g_graphs.size() >= kMaxGraphs) {
+        // bounded cache: callers that cycle through many buffers must not grow
+        // it without limit.  Wait for every launch, then drop all graphs; they
+        // are captured again on their next use.
+        if (hipDeviceSynchronize() != hipSuccess) return hip_fail(hipErrorUnknown);
+        for (auto &kv : g_graphs) hipGraphExecDestroy(kv.second);
+        g_graphs.clear();
+    }
     if (it == g_graphs.end()) {
         if (!g_capture && hipStreamCreateWithFlags(&g_capture, hipStreamNonBlocking) != hipSuccess)
             return hip_fail(hipErrorUnknown);

@@ -358,3 +358,21 @@ def test_full_size_spd_sampled(torch_cuda, n, leaf):
     ref = np.linalg.solve(A, E)
     assert np.linalg.norm(Xs - ref) / np.linalg.norm(ref) <= 1e-12
     assert np.linalg.norm(A @ Xs - E) / np.linalg.norm(E) <= 1e-12
+
+
+def test_graph_cache_stays_bounded_and_correct(torch_cuda):
+    """More distinct buffer sets than the graph cache holds: the cache is
+    emptied and rebuilt, and every call still returns the same inverse."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    n = 96
+    A = W.diag_dominant(n, seed=77)
+    dA = _dev_f(torch, A)
+    first = _host(S.invert(dA, leaf=32))
+    outs = [torch.empty_like(dA) for _ in range(80)]
+    for o in outs:
+        S.invert(dA, leaf=32, out=o)
+    torch.cuda.synchronize()
+    assert S.info() == 0
+    for o in outs:
+        assert np.array_equal(_host(o), first)
