@@ -216,12 +216,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
 // agree).  B is staged k-contiguous (Bs[n][k]) so that a lane fetches its KQ
 // B values with 16-byte LDS reads; A is staged m-contiguous (As[k][m]).
 template <int BM, int BN, int BK, int WM, int WN, typename T, int NG>
-__global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
-    constexpr int NT = 256;
+__global__ void __launch_bounds__(64 * (BM / WM) * (BN / WN), 2) gemm_fast(GroupArgs<NG> g) {
+    constexpr int NT = 64 * (BM / WM) * (BN / WN);
     constexpr int VW = 16 / sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(VW)));
     constexpr int WAVES_M = BM / WM;
-    static_assert(WAVES_M * (BN / WN) == 4, "four waves per workgroup");
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int KQ = BK / 4;
     static_assert(KQ % VW == 0, "lane chunk must be whole vectors");
@@ -298,25 +297,28 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
         for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     const int q = lane >> 4, c16 = lane & 15;
+    // B fragments are fetched one 16-byte vector (VW consecutive k) per
+    // column block at a time, which bounds their registers to TN vectors.
     auto compute = [&](int buf) {
         const T *as = &As[buf][(q * KQ) * A_LD + wm0 + c16];
         const T *bs = &Bs[buf][(wn0 + c16) * B_LD + q * KQ];
-        vec_t bv[TN][KQ / VW];
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int kc = 0; kc < KQ / VW; ++kc) {
+            vec_t bv[TN];
 #pragma unroll
-            for (int h = 0; h < KQ / VW; ++h)
-                bv[j][h] = *reinterpret_cast<const vec_t *>(bs + j * 16 * B_LD + h * VW);
+            for (int j = 0; j < TN; ++j)
+                bv[j] = *reinterpret_cast<const vec_t *>(bs + j * 16 * B_LD + kc * VW);
 #pragma unroll
-        for (int kk = 0; kk < KQ; ++kk) {
-            T a[TM];
+            for (int t = 0; t < VW; ++t) {
+                const int kk = kc * VW + t;
+                T a[TM];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) a[i] = as[kk * A_LD + i * 16];
+                for (int i = 0; i < TM; ++i) a[i] = as[kk * A_LD + i * 16];
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
+                for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = Mma<T>::mma(bv[j][kk / VW][kk % VW], a[i], acc[i][j]);
+                    for (int j = 0; j < TN; ++j) acc[i][j] = Mma<T>::mma(bv[j][t], a[i], acc[i][j]);
+            }
         }
     };
 
@@ -581,7 +583,8 @@ hipError_t launch_group(const GemmProb *probs, int count, hipStream_t s) {
     const int total = make_group<BM, BN, N>(probs, count, g);
     if (total == 0) return hipSuccess;
     if constexpr (FAST)
-        hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T, N>), dim3(total),
+                           dim3(64 * (BM / WM) * (BN / WN)), 0, s, g);
     else
         hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
     return hipGetLastError();
