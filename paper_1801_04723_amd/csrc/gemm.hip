@@ -207,8 +207,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
 // multiples of the vector width, M a multiple of the vector width and K a
 // multiple of BK -- true for every block product of the recursion when the
 // order is a multiple of 64.  The main loop then has no control flow: the
-// edge rows/columns of a tile are clamped once and masked, each thread keeps
-// one pointer per 16-byte global load and advances it by one slab per step.
+// edge rows/columns of a tile are clamped once (what they load only reaches
+// outputs the epilogue discards), each thread keeps one pointer per 16-byte
+// global load and advances it by one slab per step.
 //
 // The K slab is split into four contiguous chunks of KQ = BK/4 values, one per
 // lane group q = lane/16, and MFMA step kk consumes k = q*KQ + kk in group q
@@ -216,11 +217,12 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
 // agree).  B is staged k-contiguous (Bs[n][k]) so that a lane fetches its KQ
 // B values with 16-byte LDS reads; A is staged m-contiguous (As[k][m]).
 template <int BM, int BN, int BK, int WM, int WN, typename T, int NG>
-__global__ void __launch_bounds__(64 * (BM / WM) * (BN / WN), 2) gemm_fast(GroupArgs<NG> g) {
-    constexpr int NT = 64 * (BM / WM) * (BN / WN);
+__global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
+    constexpr int NT = 256;
     constexpr int VW = 16 / sizeof(T);
     typedef T vec_t __attribute__((ext_vector_type(VW)));
     constexpr int WAVES_M = BM / WM;
+    static_assert(WAVES_M * (BN / WN) == 4, "four waves per workgroup");
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int KQ = BK / 4;
     static_assert(KQ % VW == 0, "lane chunk must be whole vectors");
@@ -583,8 +585,7 @@ hipError_t launch_group(const GemmProb *probs, int count, hipStream_t s) {
     const int total = make_group<BM, BN, N>(probs, count, g);
     if (total == 0) return hipSuccess;
     if constexpr (FAST)
-        hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T, N>), dim3(total),
-                           dim3(64 * (BM / WM) * (BN / WN)), 0, s, g);
+        hipLaunchKernelGGL((gemm_fast<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
     else
         hipLaunchKernelGGL((gemm_kernel<BM, BN, BK, WM, WN, T, N>), dim3(total), dim3(256), 0, s, g);
     return hipGetLastError();
