@@ -105,16 +105,16 @@ def serving(rate: float, seconds: float):
     """Open-loop serving run: Poisson arrivals at `rate` for `seconds`, orders
     log-uniform in [64, 4096] padded to 64, half diagonally dominant and half
     SPD (kappa log-uniform in [10, 1e4]), 70% mixed precision with 2 Newton
-    steps and 30% FP64, leaf 128; orders below and from 1024 are served by
-    two server lanes on two streams; p50/p99 latency from arrival to
-    completion, TFLOP/s from 2n^3 per request."""
+    steps and 30% FP64, leaf 128; orders below 512, from 512 to 2047 and from
+    2048 up are served by three server lanes on three streams; p50/p99
+    latency from arrival to completion, TFLOP/s from 2n^3 per request."""
     import workloads as W
     from paper_1801_04723_amd import serve
     trace = W.serving_trace(rate=rate, duration=seconds, seed=5)
-    st = serve.run_trace(trace, leaf=128, ns_steps=2, split_n=1024)
+    st = serve.run_trace(trace, leaf=128, ns_steps=2, split_n=[512, 2048])
     st["workload"] = (f"Poisson {rate:g} req/s for {seconds:g} s, n log-uniform 64..4096 (x64), "
                       "50% diag-dominant / 50% SPD, 70% mixed FP32+2 Newton / 30% FP64, leaf 128; "
-                      "two server lanes on two streams (n < 1024, n >= 1024)")
+                      "three server lanes on three streams (n < 512, 512 <= n < 2048, n >= 2048)")
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
 
 

@@ -61,26 +61,28 @@ def percentile(xs, p):
 
 def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 << 30,
               max_active: int = 64, max_ticks_in_flight: int = 64, pool: MatrixPool | None = None,
-              split_n: int | None = None):
+              split_n=None):
     """Serves `trace` (list of dicts with t, n, kind, kappa, mixed) and returns
     latency / throughput statistics.
 
-    With split_n set, requests of order >= split_n go to a second server on a
-    second stream (a quarter of the pool stays with the small-order lane), so
-    the long step sequences of large requests and the many short steps of
-    small ones run side by side instead of taking turns in one stream; each
-    request's result is the same either way."""
+    split_n (an order or an increasing list of orders) divides the requests
+    into lanes by order; each lane is its own server on its own stream, with
+    the pool divided evenly.  The long step sequences of large requests and
+    the many short steps of small ones then run side by side instead of
+    taking turns in one stream; each request's result is the same either way."""
     import torch
     pool = pool or MatrixPool()
     # materialise the inputs before the clock starts
     for r in trace:
         pool.get(r["n"], r["kind"], r["kappa"])
     torch.cuda.synchronize()
-    if split_n is None:
+    bounds = [] if split_n is None else sorted([split_n] if isinstance(split_n, int) else list(split_n))
+    if not bounds:
         lanes = [(Server(pool_bytes, max_active, leaf, ns_steps), torch.cuda.current_stream())]
     else:
-        lanes = [(Server(pool_bytes // 4, max_active, leaf, ns_steps), torch.cuda.Stream()),
-                 (Server(pool_bytes - pool_bytes // 4, max_active, leaf, ns_steps), torch.cuda.Stream())]
+        share = pool_bytes // (len(bounds) + 1)
+        lanes = [(Server(share, max_active, leaf, ns_steps), torch.cuda.Stream())
+                 for _ in range(len(bounds) + 1)]
     inflight = [collections.deque() for _ in lanes]
     lat, flops, statuses = [], 0.0, collections.Counter()
     outs = {}
@@ -93,7 +95,7 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
             r = trace[nxt]
             a = pool.get(r["n"], r["kind"], r["kappa"])
             x = torch.empty_like(a)
-            lane = 0 if split_n is None or r["n"] < split_n else 1
+            lane = sum(1 for b in bounds if r["n"] >= b)
             lanes[lane][0].submit(a, x, MIXED_FP32 if r["mixed"] else FP64, tag=nxt)
             outs[nxt] = x
             nxt += 1
@@ -135,5 +137,5 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
         "ns_steps": ns_steps,
         "max_active": max_active,
         "lanes": len(lanes),
-        "split_n": split_n,
+        "split_n": bounds,
     }

@@ -104,11 +104,15 @@ def test_singular_request_does_not_disturb_others(torch_cuda):
     assert torch.equal(outs[2], S.invert_mixed(good[1], leaf=64, ns_steps=2))
 
 
-def test_serving_loop_short_trace(torch_cuda):
+@pytest.mark.parametrize("split", [None, [128, 256]])
+def test_serving_loop_short_trace(torch_cuda, split):
+    """One lane, and three lanes on three streams split by order."""
     import paper_1801_04723_amd.serve as serve
     import workloads as W
     trace = W.serving_trace(rate=100.0, duration=0.5, seed=11, n_max=512)
-    stats = serve.run_trace(trace, leaf=64, ns_steps=2, pool_bytes=4 << 30, max_active=16)
+    stats = serve.run_trace(trace, leaf=64, ns_steps=2, pool_bytes=4 << 30, max_active=16,
+                            split_n=split)
     assert stats["requests"] == len(trace) > 10
     assert stats["status_counts"] == {0: len(trace)}
     assert stats["p50_ms"] <= stats["p99_ms"] <= stats["max_ms"]
+    assert stats["lanes"] == (1 if split is None else 3)
