@@ -55,6 +55,8 @@ def parse():
                    help="order of the mixed-precision vs FP64 comparison (0 disables it)")
     p.add_argument("--mixed-leaf", type=int, default=256)
     p.add_argument("--mixed-reps", type=int, default=2)
+    p.add_argument("--gemm-sweep", action="store_true",
+                   help="only time spin_gemm alone (FP64, FP32, BF16, bf16x3; h = 2048, 4096, 8192) and exit")
     p.add_argument("--calib-copy", action="store_true",
                    help="run one 512 MiB device-to-device copy first (HBM counter calibration)")
     return p.parse_args()
@@ -221,6 +223,38 @@ def roofline_from_trace(recs, n_steps: int):
     }, breakdown
 
 
+def gemm_sweep():
+    """Standalone block products D = A B (h x h x h, column-major, ld h) in each
+    flavour: mean of 20 back-to-back calls after 3 warm-ups, HIP events on the
+    launch stream.  TFLOP/s of 2h^3 (bf16x3 issues three times that)."""
+    import torch
+
+    import paper_1801_04723_amd as spin
+    rows = []
+    for h in (2048, 4096, 8192):
+        for mode, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16", torch.float32),
+                         ("bf16x3", torch.float32)):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(h)
+            a = torch.rand(h, h, dtype=dt, device="cuda", generator=g)
+            b = torch.rand(h, h, dtype=dt, device="cuda", generator=g)
+            d = torch.empty(h, h, dtype=dt, device="cuda")
+            call = lambda: spin.gemm_cm(h, h, h, 1.0, a, h, b, h, 0.0, None, h, d, h, False, mode)  # noqa: E731
+            for _ in range(3):
+                call()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 20
+            rows.append({"h": h, "mode": mode, "ms": round(ms, 4), "tflops": round(2.0 * h ** 3 / ms / 1e9, 2)})
+            del a, b, d
+    return rows
+
+
 def finite_json(x):
     """The output with every NaN or infinity replaced by None (strict JSON)."""
     import math
@@ -244,6 +278,9 @@ def main():
     import paper_1801_04723_amd as spin
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.gemm_sweep:
+        print(json.dumps({"gemm_sweep": gemm_sweep()}), flush=True)
+        return
     dev = torch.device("cuda:0")
     seed = args.seed if args.seed is not None else {"spd": 2, "dd": 3, "spdk": 4}[args.kind]
     n, leaf = args.n, args.leaf

@@ -250,11 +250,24 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
                 a.used[row] = 1;
         }
         if (nb < L) {
-            // rows of Q (the pivot rows) in lane order, one column per pass
-            for (int j = t / NBMAX; j < L; j += NT / NBMAX) {
-                const int c = t % NBMAX;
-                if (c < nb && (j < k0 || j >= k0 + nb))
-                    a.Q[c + (int64_t)j * nb] = a.Z[prow_s[c] + (int64_t)j * a.ldz];
+            // rows of Q (the pivot rows) in lane order, NT / NBMAX columns per
+            // pass; four passes' loads are issued before their stores
+            constexpr int JS = NT / NBMAX;
+            const int c = t % NBMAX;
+            const int rp = c < nb ? prow_s[c] : 0;
+            const bool cok = c < nb && (unsigned)rp < (unsigned)L;
+            for (int j0 = t / NBMAX; j0 < L; j0 += 4 * JS) {
+                double v[4];
+                bool ok[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int j = j0 + u * JS;
+                    ok[u] = cok && j < L && (j < k0 || j >= k0 + nb);
+                    v[u] = ok[u] ? a.Z[rp + (int64_t)j * a.ldz] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (ok[u]) a.Q[c + (int64_t)(j0 + u * JS) * nb] = v[u];
             }
         }
     }
