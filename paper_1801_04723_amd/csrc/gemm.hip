@@ -370,7 +370,10 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
 // rounded to BF16 (round to nearest even) while they are staged into LDS,
 // k-contiguous per m (A) or n (B) row so that each lane fetches its eight k
 // with one 16-byte read; the 80-byte row pitch spreads the 16 rows a
-// quarter-wave reads over all 64 banks.  X3 splits every operand into
+// quarter-wave reads over all 64 banks, and the four 16-byte k chunks of a
+// row are stored in the order chunk ^ ((row >> 4) & 3), which spreads the
+// stores of lanes 64 or 80 bytes x 4 rows apart over the banks while every
+// 16-row read block keeps one order.  X3 splits every operand into
 // hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32) and
 // accumulates hi*hi + lo*hi + hi*lo, about 16 significant bits per operand
 // (the lo*lo term, of relative size 2^-16, is dropped).
@@ -395,7 +398,8 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
     constexpr int NP = X3 ? 2 : 1;         // hi (and lo) planes
     static_assert(KPA >= 1 && KPB % 4 == 0, "slab/thread mismatch");
     typedef typename BfVec<KPA>::type va_t;
-    typedef typename BfVec<KPB>::type vb_t;
+    static_assert(BK == 32, "four 16-byte k chunks per row");
+    auto swz = [](int row) { return (row >> 4) & 3; };
 
     __shared__ __attribute__((aligned(16))) __bf16 As[2][NP][BM * LDK];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NP][BN * LDK];
@@ -472,18 +476,27 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
                 hi[j] = h;
                 if (X3) lo[j] = (__bf16)(ra[j][i] - (float)h);
             }
-            *reinterpret_cast<va_t *>(&As[buf][0][(4 * mq + i) * LDK + kq * KPA]) = hi;
-            if (X3) *reinterpret_cast<va_t *>(&As[buf][NP - 1][(4 * mq + i) * LDK + kq * KPA]) = lo;
+            const int row = 4 * mq + i, k = kq * KPA;
+            const int off = row * LDK + (((k >> 3) ^ swz(row)) << 3) + (k & 7);
+            *reinterpret_cast<va_t *>(&As[buf][0][off]) = hi;
+            if (X3) *reinterpret_cast<va_t *>(&As[buf][NP - 1][off]) = lo;
         }
-        vb_t hi, lo;
+        typedef __bf16 bc_t __attribute__((ext_vector_type(KPB < 8 ? KPB : 8)));
+        constexpr int CW = KPB < 8 ? KPB : 8;  // elements per store
 #pragma unroll
-        for (int j = 0; j < KPB; ++j) {
-            const __bf16 h = (__bf16)rb[j];
-            hi[j] = h;
-            if (X3) lo[j] = (__bf16)(rb[j] - (float)h);
+        for (int h0 = 0; h0 < KPB; h0 += CW) {
+            bc_t hi, lo;
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                const __bf16 h = (__bf16)rb[h0 + j];
+                hi[j] = h;
+                if (X3) lo[j] = (__bf16)(rb[h0 + j] - (float)h);
+            }
+            const int k = bk + h0;
+            const int off = bn * LDK + (((k >> 3) ^ swz(bn)) << 3) + (k & 7);
+            *reinterpret_cast<bc_t *>(&Bs[buf][0][off]) = hi;
+            if (X3) *reinterpret_cast<bc_t *>(&Bs[buf][NP - 1][off]) = lo;
         }
-        *reinterpret_cast<vb_t *>(&Bs[buf][0][bn * LDK + bk]) = hi;
-        if (X3) *reinterpret_cast<vb_t *>(&Bs[buf][NP - 1][bn * LDK + bk]) = lo;
     };
 
     f4_t acc[TM][TN];
@@ -498,11 +511,15 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
 #pragma unroll
         for (int pl = 0; pl < NP; ++pl) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
-                a[pl][i] = *reinterpret_cast<const bf8_t *>(&As[buf][pl][(wm0 + 16 * i + c16) * LDK + 8 * g4]);
+            for (int i = 0; i < TM; ++i) {
+                const int row = wm0 + 16 * i + c16;
+                a[pl][i] = *reinterpret_cast<const bf8_t *>(&As[buf][pl][row * LDK + ((g4 ^ swz(row)) << 3)]);
+            }
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-                b[pl][j] = *reinterpret_cast<const bf8_t *>(&Bs[buf][pl][(wn0 + 16 * j + c16) * LDK + 8 * g4]);
+            for (int j = 0; j < TN; ++j) {
+                const int row = wn0 + 16 * j + c16;
+                b[pl][j] = *reinterpret_cast<const bf8_t *>(&Bs[buf][pl][row * LDK + ((g4 ^ swz(row)) << 3)]);
+            }
         }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
