@@ -180,9 +180,11 @@ int spin_server_admit(spin_server *srv);
 /* Admits, then enqueues one step of every admitted request; returns the
  * number of admitted, unfinished requests or a negative SPIN_E_* code. */
 int spin_server_tick(spin_server *srv, spin_stream_t stream);
-/* Non-blocking: writes up to cap (tag, status) pairs of requests whose work
- * has completed since the last poll and frees their pool space; returns the
- * count. */
+/* Does not wait for queued work: writes up to cap (tag, status) pairs of
+ * requests whose work has completed since the last poll and frees their pool
+ * space; returns the count, or a negative SPIN_E_* code.  A finished
+ * request's status words are read on the server's own non-blocking stream.
+ * A status of SPIN_E_HIP means they could not be read. */
 int64_t spin_server_poll(spin_server *srv, int64_t *tags, int *info, int64_t cap);
 int spin_server_stats(spin_server *srv, int64_t *queued, int64_t *active, size_t *pool_used);
 /* Pool bytes one request of order n needs (0 for invalid arguments). */

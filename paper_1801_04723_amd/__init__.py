@@ -405,6 +405,8 @@ class Server:
         tags = (_i64 * cap)()
         info = (ctypes.c_int * cap)()
         cnt = lib().spin_server_poll(self._h, tags, info, cap)
+        if cnt < 0:
+            raise SpinError(int(cnt), "spin_server_poll")
         out = [(int(tags[i]), int(info[i])) for i in range(cnt)]
         for t, _ in out:
             self._keep.pop(t, None)

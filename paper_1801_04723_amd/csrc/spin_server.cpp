@@ -241,6 +241,9 @@ struct spin_server {
     std::deque<Request *> queue;
     std::vector<Request *> active;  // admission order
     std::vector<std::pair<int64_t, int>> completed;
+    // private non-blocking stream for reading finished requests' status
+    // words: a copy there waits for nothing but itself
+    hipStream_t poll_stream = nullptr;
     spin_server(size_t b, int m, int64_t l, int s)
         : pool_bytes(b), max_active(m), leaf(l), ns_steps(s), alloc(b) {}
 };
@@ -289,6 +292,7 @@ void spin_server_destroy(spin_server *s) {
         hipDeviceSynchronize();
         hipFree(s->pool);
     }
+    if (s->poll_stream) hipStreamDestroy(s->poll_stream);
     for (Request *r : s->active) {
         if (r->done) hipEventDestroy(r->done);
         delete r;
@@ -392,9 +396,18 @@ int64_t spin_server_poll(spin_server *s, int64_t *tags, int *info, int64_t cap) 
     for (auto it = s->active.begin(); it != s->active.end();) {
         Request *r = *it;
         if (r->done && hipEventQuery(r->done) == hipSuccess) {
+            if (!s->poll_stream &&
+                hipStreamCreateWithFlags(&s->poll_stream, hipStreamNonBlocking) != hipSuccess) {
+                s->poll_stream = nullptr;
+                return hipfail(hipErrorUnknown);
+            }
             int h[2] = {INT_MAX, INT_MAX};
-            hipMemcpy(h, r->ws, sizeof(h), hipMemcpyDeviceToHost);
-            const int code = (h[0] != INT_MAX) ? h[0] : (h[1] != INT_MAX) ? h[1] : 0;
+            hipError_t e = hipMemcpyAsync(h, r->ws, sizeof(h), hipMemcpyDeviceToHost, s->poll_stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->poll_stream);
+            const int code = (e != hipSuccess)  ? SPIN_E_HIP
+                             : (h[0] != INT_MAX) ? h[0]
+                             : (h[1] != INT_MAX) ? h[1]
+                                                 : 0;
             s->completed.emplace_back(r->tag, code);
             hipEventDestroy(r->done);
             s->alloc.release(r->ws_off, r->ws_bytes);
