@@ -474,11 +474,12 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
     }
     if (e == hipSuccess) e = frob2(R, n, n, n, parts, misc + 2, s);
     if (e == hipSuccess) e = frob2(Ainv, ldx, n, n, parts, misc + 3, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // copies ordered on the caller's stream (not the null stream), then wait for it
     double h_norms[kNormSlots + 4];
     int h_status[2];
-    if (e == hipSuccess) e = hipMemcpy(h_norms, norms, sizeof(h_norms), hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(h_status, status, sizeof(h_status), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_norms, norms, sizeof(h_norms), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_status, status, sizeof(h_status), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e);
     const double na = std::sqrt(h_norms[kNormSlots + 0]);
     const double nx0 = std::sqrt(h_norms[kNormSlots + 1]);
@@ -524,8 +525,8 @@ int spin_info(spin_stream_t stream) {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_ws.find(s);
         if (it == g_ws.end() || !it->second.base) return SPIN_OK;
-        if (hipStreamSynchronize(s) != hipSuccess) return hip_fail(hipErrorUnknown);
-        if (hipMemcpy(h, it->second.base, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpyAsync(h, it->second.base, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
             return hip_fail(hipErrorUnknown);
     }
     if (h[0] != INT32_MAX) return h[0];
@@ -551,9 +552,9 @@ int spin_residual(const double *A, int64_t n, int64_t lda, const double *X, int6
     if (e == hipSuccess) e = frob2(R, n, n, n, parts, norms + 0, s);
     if (e == hipSuccess) e = frob2(A, lda, n, n, parts, norms + 1, s);
     if (e == hipSuccess) e = frob2(X, ldx, n, n, parts, norms + 2, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     double h[3];
-    if (e == hipSuccess) e = hipMemcpy(h, norms, sizeof(h), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, norms, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e);
     *rho = std::sqrt(h[0]) / (std::sqrt(h[1]) * std::sqrt(h[2]));
     return SPIN_OK;
