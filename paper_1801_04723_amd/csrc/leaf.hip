@@ -117,7 +117,14 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
     __shared__ double rowbuf[2][NBMAX];
     __shared__ int pivstep[LMAX];  // step at which a row was the pivot, or -1
     __shared__ int prow_s[NBMAX];  // pivot row of each step
-    const int t = threadIdx.x, tr = t >> 4, tc = t & 15, lane = t & 63;
+    // Thread t holds rows tr + TR r of columns tc + 16 q.  Whole leaves put
+    // the 16 threads of a row group in one wave (t = 16 tr + tc), so one wave
+    // publishes the pivot row.  Panels put TR consecutive rows of one column
+    // in consecutive lanes (t = TR tc + tr): their loads of the panel and
+    // stores of Z and Up then cover whole column segments, which outweighs
+    // spreading the pivot-row publication over all waves.
+    const int t = threadIdx.x, lane = t & 63;
+    const int tr = WHOLE ? t >> 4 : t % TR, tc = WHOLE ? t & 15 : t / TR;
     const int L = a.L;
     const int k0 = WHOLE ? 0 : a.k0;
     const int nb = WHOLE ? a.L : a.nb;
@@ -251,23 +258,24 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
         }
         if (nb < L) {
             // rows of Q (the pivot rows) in lane order, NT / NBMAX columns per
-            // pass; four passes' loads are issued before their stores
+            // pass; every pass's load is issued before the first store
             constexpr int JS = NT / NBMAX;
-            const int c = t % NBMAX;
+            constexpr int JN = LMAX / JS;
+            static_assert(JN * JS == LMAX, "passes must cover the rows");
+            const int c = t % NBMAX, j0 = t / NBMAX;
             const int rp = c < nb ? prow_s[c] : 0;
             const bool cok = c < nb && (unsigned)rp < (unsigned)L;
-            for (int j0 = t / NBMAX; j0 < L; j0 += 4 * JS) {
-                double v[4];
-                bool ok[4];
+            double v[JN];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int j = j0 + u * JS;
-                    ok[u] = cok && j < L && (j < k0 || j >= k0 + nb);
-                    v[u] = ok[u] ? a.Z[rp + (int64_t)j * a.ldz] : 0.0;
-                }
+            for (int u = 0; u < JN; ++u) {
+                const int j = j0 + u * JS;
+                const bool ok = cok && j < L && (j < k0 || j >= k0 + nb);
+                v[u] = ok ? a.Z[rp + (int64_t)j * a.ldz] : 0.0;
+            }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (ok[u]) a.Q[c + (int64_t)(j0 + u * JS) * nb] = v[u];
+            for (int u = 0; u < JN; ++u) {
+                const int j = j0 + u * JS;
+                if (cok && j < L && (j < k0 || j >= k0 + nb)) a.Q[c + (int64_t)j * nb] = v[u];
             }
         }
     }
