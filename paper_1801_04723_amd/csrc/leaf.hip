@@ -46,12 +46,13 @@ constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;
 constexpr int kDppMirror = 0x140;
 
+// Every control used here reads a lane of the same row, so all lanes are
+// written and the move needs no initial value.
 template <int CTRL>
 __device__ inline double dpp_f64(double x) {
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(x) & 0xffffffff), CTRL,
-                                               0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(__double_as_longlong(x) >> 32), CTRL, 0xf,
-                                               0xf, false);
+    const int lo =
+        __builtin_amdgcn_mov_dpp((int)(__double_as_longlong(x) & 0xffffffff), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(__double_as_longlong(x) >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
