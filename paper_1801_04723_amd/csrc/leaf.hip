@@ -497,10 +497,13 @@ hipError_t gj2d_launch(const LeafArgs &la, hipStream_t s) {
 }
 
 // Threads per row group of the 2-D kernel for whole leaves of order <= 128
-// and for panels of leaves of order <= 256 (measured best: 32, i.e. 512
-// threads, on MI355X).
+// and for panels of leaves of order <= 256 and <= 512 (measured best on
+// MI355X: 32, i.e. 512 threads, in all three; a 512-row panel takes 147 us
+// with 512 threads against 169 us with 1024, a 256-row panel 93 us against
+// 110 us with 256 or 1024).
 constexpr int kLeaf128TR = 32;
 constexpr int kPanel256TR = 32;
+constexpr int kPanel512TR = 32;
 
 template <typename TI, typename TO>
 hipError_t whole_dispatch(const LeafArgs &la, hipStream_t s, const char **name) {
@@ -627,7 +630,7 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                 if (L <= 256)
                     e = gj2d_launch<kPanel256TR, 256 / kPanel256TR, 4, false, double, double>(la, s);
                 else
-                    e = gj2d_launch<64, 8, 4, false, double, double>(la, s);
+                    e = gj2d_launch<kPanel512TR, 512 / kPanel512TR, 4, false, double, double>(la, s);
             } else {
                 e = panel_launch(pa, s);
             }
