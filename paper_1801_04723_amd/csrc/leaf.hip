@@ -131,6 +131,11 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
     const int nb = WHOLE ? a.L : a.nb;
 
     for (int i = t; i < LMAX; i += NT) pivstep[i] = -1;
+    // Panel mode reads the panel and the pivot rows from `in` when it is set
+    // (the first panel of an FP64 leaf, straight from the leaf's input) and
+    // from Z otherwise; it always writes Z.
+    const double *src = WHOLE ? nullptr : (a.in ? static_cast<const double *>(a.in) : a.Z);
+    const int64_t lds = WHOLE ? 0 : (a.in ? a.ldi : a.ldz);
     double z[RR][RC];
 #pragma unroll
     for (int r = 0; r < RR; ++r)
@@ -142,7 +147,7 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
                 if (WHOLE)
                     v = (double)static_cast<const TI *>(a.in)[row + (int64_t)col * a.ldi];
                 else
-                    v = a.Z[row + (int64_t)(k0 + col) * a.ldz];
+                    v = src[row + (int64_t)(k0 + col) * lds];
             }
             z[r][q] = v;
         }
@@ -271,7 +276,7 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
             for (int u = 0; u < JN; ++u) {
                 const int j = j0 + u * JS;
                 const bool ok = cok && j < L && (j < k0 || j >= k0 + nb);
-                v[u] = ok ? a.Z[rp + (int64_t)j * a.ldz] : 0.0;
+                v[u] = ok ? src[rp + (int64_t)j * lds] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < JN; ++u) {
@@ -593,7 +598,10 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
     int *used = reinterpret_cast<int *>(p);
 
     const int nblk = (int)(((int64_t)L * L + 255) / 256);
-    {
+    // Up to order 512 an FP64 input is read in place by the first panel and
+    // its update (which writes Z); otherwise it is copied into Z first.
+    const bool direct = L <= 512 && in_dt == kF64;
+    if (!direct) {
         LaunchInfo li{"leaf_copy_in", 0.0, (in_dt == kF64 ? 16.0 : 12.0) * Ld * Ld};
         cb(li, 0);
         if (in_dt == kF64)
@@ -623,6 +631,10 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                 la.ldz = L;
                 la.k0 = k0;
                 la.nb = w;
+                if (direct && k0 == 0) {
+                    la.in = in;
+                    la.ldi = ldi;
+                }
                 la.used = used;
                 la.rsel = rsel;
                 la.Up = Up;
@@ -653,10 +665,15 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
         if (k0 > 0)
             pr[np++] = GemmProb{Up, Q, Z, Z, (int64_t)L, (int64_t)w, (int64_t)L, (int64_t)L,
                                 L, k0, w, 0, 1.0, 1.0};
-        if (k0 + w < L)
-            pr[np++] = GemmProb{Up, Q + (int64_t)(k0 + w) * w, Z + (int64_t)(k0 + w) * L,
-                                Z + (int64_t)(k0 + w) * L, (int64_t)L, (int64_t)w, (int64_t)L,
-                                (int64_t)L, L, L - k0 - w, w, 0, 1.0, 1.0};
+        if (k0 + w < L) {
+            // the columns right of the first panel still live in the input
+            const bool from_in = direct && k0 == 0;
+            const double *c0 = from_in ? static_cast<const double *>(in) + (int64_t)(k0 + w) * ldi
+                                       : Z + (int64_t)(k0 + w) * L;
+            pr[np++] = GemmProb{Up, Q + (int64_t)(k0 + w) * w, c0, Z + (int64_t)(k0 + w) * L,
+                                (int64_t)L, (int64_t)w, from_in ? ldi : (int64_t)L, (int64_t)L,
+                                L, L - k0 - w, w, 0, 1.0, 1.0};
+        }
         LaunchInfo gi{};
         cb(gi, 0);
         hipError_t e = gemm_launch(pr, np, kF64, s, &gi);
