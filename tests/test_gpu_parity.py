@@ -212,6 +212,31 @@ def test_invert_fp64_parity(torch_cuda, kind, n, leaf):
     assert S.residual(dA, _dev_f(torch, X)) <= 1e-12
 
 
+@pytest.mark.parametrize("n,lda,leaf", [(600, 611, 300), (1000, 1003, 512), (515, 520, 515)])
+def test_invert_fp64_panel_leaves_padded_lda(torch_cuda, n, lda, leaf):
+    """FP64 leaves above order 128 are read in place from the input (the
+    first panel and its update use the input's leading dimension): padded
+    input and output, NaN in the input padding, the output padding kept."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    A = W.spd_gram(n, seed=n + 5)
+    bufA = torch.full((n, lda), float("nan"), dtype=torch.float64, device="cuda")
+    bufA[:, :n] = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+    dA = bufA.t()[:n, :]                      # column-major view with ld lda
+    bufX = torch.full((n, lda + 2), 7.0, dtype=torch.float64, device="cuda")
+    dX = bufX.t()[:n, :]
+    S.invert(dA, leaf=leaf, out=dX)
+    assert S.info() == 0
+    X = _host(dX)
+    ref, info = oracle.strassen_inv(A, leaf)
+    assert info == 0
+    err = np.linalg.norm(X - ref) / np.linalg.norm(ref)
+    assert err <= max(1e-13, 100 * _kappa(A) * U), err
+    assert oracle.residual(A, X) <= 1e-12
+    assert bool(torch.all(bufX[:, n:] == 7.0))
+    assert bool(torch.all(torch.isnan(bufA[:, n:])))   # the input is never written
+
+
 @pytest.mark.parametrize("n,eps", [(300, 1e-6), (1024, 1e-9)])
 def test_device_residual_matches_host(torch_cuda, n, eps):
     import paper_1801_04723_amd as S
