@@ -1,0 +1,85 @@
+"""Full-size cases of the n = 16384 workloads (leaf sweep end points and the
+mixed-precision comparison), generated on the GPU.
+
+The CPU oracle cannot invert an n = 16384 matrix in test time, so these cases
+are checked through properties that hold at any size, with arithmetic that is
+not the library's: the library's residual rho, then sampled columns x_j of the
+inverse against A x_j = e_j formed by torch's own FP64 product, and (mixed
+modes) against columns of torch's LU solve.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N = 16384
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _sampled_columns(torch, n, k, seed):
+    g = np.random.default_rng(seed)
+    return torch.from_numpy(np.sort(g.choice(n, size=k, replace=False))).cuda()
+
+
+def _column_residual(torch, A, X, cols):
+    """max_j |A x_j - e_j|_2 / (|A|_F |x_j|_2) over the sampled columns."""
+    Xs = X[:, cols].contiguous()
+    E = torch.zeros_like(Xs)
+    E[cols, torch.arange(len(cols), device=Xs.device)] = 1.0
+    R = A @ Xs - E
+    return float((R.norm(dim=0) / (A.norm() * Xs.norm(dim=0))).max())
+
+
+@pytest.mark.parametrize("leaf", [128, 2048])
+def test_diag_dominant_16384_leaf_ends(torch_cuda, leaf):
+    """Leaf sweep end points: U(-1, 1) + n I, n = 16384, leaf 128 and 2048."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    A = W.torch_diag_dominant(N, seed=16384 + leaf)
+    X = S.invert(A, leaf=leaf)
+    assert S.info() == 0
+    assert S.residual(A, X) <= 1e-12
+    cols = _sampled_columns(torch, N, 8, leaf)
+    assert _column_residual(torch, A, X, cols) <= 1e-14
+    del A, X
+    S.release()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode,steps", [("fp32", 2), ("bf16x3", 3)])
+def test_mixed_spd_16384(torch_cuda, mode, steps):
+    """Mixed precision at full size: SPD Q diag(lam) Q^T with lam over
+    [1, 1e4], leaf 256; FP64 refinement reaches rho <= 1e-12 from rho <= 1e-3,
+    and sampled columns differ from torch's LU solve by no more than their
+    residual allows."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    A = W.torch_spd_spectrum(N, seed=4, kappa=1e4)
+    X, rep = S.invert_mixed(A, leaf=256, mode=mode, ns_steps=steps, report=True)
+    assert rep["status"] == 0, rep
+    assert rep["rho_before"] <= 1e-3, rep
+    assert rep["rho_after"] <= 1e-12, rep
+    cols = _sampled_columns(torch, N, 6, 7)
+    # the refined result meets the mixed-mode residual target, column by column
+    assert _column_residual(torch, A, X, cols) <= 1e-12
+    E = torch.zeros((N, len(cols)), dtype=torch.float64, device="cuda")
+    E[cols, torch.arange(len(cols), device="cuda")] = 1.0
+    ref = torch.linalg.solve(A, E)
+    Xs = X[:, cols].contiguous()
+    # A is SPD with smallest eigenvalue 1, so |x - A^-1 e| <= |A x - e| for
+    # every column; the reference solve adds its own error, kappa * O(u).
+    res = float((A @ Xs - E).norm())
+    diff = float((Xs - ref).norm())
+    assert diff <= 1.01 * res + 1e4 * 1e-13 * float(ref.norm()), (diff, res)
+    del A, X, Xs, E, ref
+    S.release()
+    torch.cuda.empty_cache()
