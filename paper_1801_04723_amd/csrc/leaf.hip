@@ -5,7 +5,7 @@
 // partial pivoting, always in FP64 (also when the surrounding products run in
 // FP32).
 //
-// Both tiers use implicit pivoting: rows are never moved.  Step k picks the
+// Every tier uses implicit pivoting: rows are never moved.  Step k picks the
 // unused row p with the largest |z[p][k]| (ties to the smallest row index),
 // scales row p by 1/pivot and eliminates column k from every other row.  The
 // storage is in place: after step k the slot of column k holds column p of
@@ -19,12 +19,16 @@
 //   column k publish it to LDS, every wave finds the pivot redundantly (DPP
 //   max, then ballots for the smallest row index), the owners of the pivot
 //   row publish the scaled row, and every thread applies the rank-1 update.
-// Tier 2 (L > 128): blocked Gauss-Jordan over column panels of width NB.  One
-//   workgroup eliminates a panel (all L rows x NB columns in registers, the
-//   same 2-D kernel) and emits the panel's transformation U' = U - E (E =
-//   unit entries at the pivot rows) and the pivot rows Q of the other
+// Tier 2 (L > 128): blocked Gauss-Jordan over column panels of width NB on a
+//   working copy Z.  One workgroup eliminates a panel (all L rows x NB
+//   columns in registers) and emits the panel's transformation U' = U - E
+//   (E = unit entries at the pivot rows) and the pivot rows Q of the other
 //   columns; those columns are then updated by one grouped matrix-core
 //   product  Z[:, out] += U' * Q.  A final pass writes the permuted result.
+//   Up to order 512 the panel kernel is the same 2-D kernel, and an FP64
+//   leaf is not copied first: the first panel and its product read the
+//   leaf's input in place.  Above 512 a rotating-slot panel kernel works on
+//   narrower panels and the input is copied into Z.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -88,10 +92,11 @@ __device__ inline double wave_max(double x) {
 //   4. every thread applies the rank-1 update to its registers.
 // WHOLE = true : the block is a whole leaf (columns = rows), read from `in`
 //                and written to `out` with the pivot permutation applied.
-// WHOLE = false: the block is one column panel of a blocked elimination on
-//                the FP64 scratch copy Z; the kernel writes the panel back,
-//                its transformation U' = U - E, the used-row flags and the
-//                gathered pivot rows Q of the other columns.
+// WHOLE = false: the block is one column panel of a blocked elimination
+//                whose working copy is Z (the first panel of an FP64 leaf
+//                reads the leaf's input instead); the kernel writes the panel
+//                to Z, its transformation U' = U - E, the used-row flags and
+//                the gathered pivot rows Q of the other columns.
 struct LeafArgs {
     const void *in;
     int64_t ldi;
