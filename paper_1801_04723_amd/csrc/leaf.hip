@@ -156,11 +156,15 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
             }
             z[r][q] = v;
         }
-    bool usd[CPL];
+    // Bit j: row lane + 64 j is used (or beyond L).  A per-lane integer keeps
+    // the flags in a vector register; as bool arrays they become wave-wide
+    // lane masks whose per-step merges cost scalar instructions, and the
+    // scalar unit is shared by the CU's SIMDs.
+    int usdm = 0;
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const int row = lane + 64 * j;
-        usd[j] = row >= L || (!WHOLE && k0 > 0 && a.used[row] != 0);
+        if (row >= L || (!WHOLE && k0 > 0 && a.used[row] != 0)) usdm |= 1 << j;
     }
     int bad = 0;
     __syncthreads();
@@ -185,8 +189,9 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
             for (int j = 0; j < CPL; ++j) {
                 const double av = fabs(colbuf[buf][lane + 64 * j]);
                 const bool fin = av <= DBL_MAX;
-                nf |= (!usd[j] && !fin);
-                key[j] = usd[j] ? -1.0 : (fin ? av : -0.5);
+                const bool u = (usdm >> j) & 1;
+                nf |= (!u && !fin);
+                key[j] = u ? -1.0 : (fin ? av : -0.5);
             }
             double lm = key[0];
 #pragma unroll
@@ -200,9 +205,7 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
             }
             p = __builtin_amdgcn_readfirstlane(p);
             if ((__any(nf) || !(best > 0.0)) && bad == 0) bad = c + 1;
-#pragma unroll
-            for (int j = 0; j < CPL; ++j)
-                if (lane + 64 * j == p) usd[j] = true;
+            usdm |= (p & 63) == lane ? 1 << (p >> 6) : 0;
             const double pinv = 1.0 / colbuf[buf][p];
             if (tr == p % TR) {
                 const int rp = p / TR;
