@@ -120,6 +120,9 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
     constexpr int CPL = LMAX / 64;
     static_assert(CPL * 64 == LMAX, "rows must cover whole waves");
     __shared__ double colbuf[2][LMAX];
+    // Panels: the multipliers, i.e. column c with 0 at the pivot row (the
+    // pivot row is scaled in place instead), so the update needs no select.
+    __shared__ double fbuf[2][LMAX];
     __shared__ double rowbuf[2][NBMAX];
     __shared__ int pivstep[LMAX];  // step at which a row was the pivot, or -1
     __shared__ int prow_s[NBMAX];  // pivot row of each step
@@ -179,6 +182,7 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
 #pragma unroll
                 for (int r = 0; r < RR; ++r) {
                     colbuf[buf][tr + TR * r] = z[r][cb];
+                    if (!WHOLE) fbuf[buf][tr + TR * r] = z[r][cb];
                     z[r][cb] = 0.0;
                 }
             }
@@ -222,12 +226,26 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
 #pragma unroll
                 for (int r = 0; r < RR; ++r) {
                     if (r == rp) {
+                        if (WHOLE) {
 #pragma unroll
-                        for (int q = 0; q < RC; ++q) {
-                            rowbuf[buf][tc + 16 * q] = z[r][q] * pinv;
-                            z[r][q] = 0.0;
+                            for (int q = 0; q < RC; ++q) {
+                                rowbuf[buf][tc + 16 * q] = z[r][q] * pinv;
+                                z[r][q] = 0.0;
+                            }
+                            if (tc == cc) rowbuf[buf][c] = pinv;
+                        } else {
+                            // scaled in place; its multiplier becomes 0
+#pragma unroll
+                            for (int q = 0; q < RC; ++q) {
+                                z[r][q] = z[r][q] * pinv;
+                                rowbuf[buf][tc + 16 * q] = z[r][q];
+                            }
+                            if (tc == cc) {
+                                rowbuf[buf][c] = pinv;
+                                z[r][cb] = pinv;
+                                fbuf[buf][p] = 0.0;
+                            }
                         }
-                        if (tc == cc) rowbuf[buf][c] = pinv;
                     }
                 }
             }
@@ -238,7 +256,8 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
             __syncthreads();
             double f[RR], rv[RC];
 #pragma unroll
-            for (int r = 0; r < RR; ++r) f[r] = (tr + TR * r == p) ? -1.0 : colbuf[buf][tr + TR * r];
+            for (int r = 0; r < RR; ++r)
+                f[r] = WHOLE ? ((tr + TR * r == p) ? -1.0 : colbuf[buf][tr + TR * r]) : fbuf[buf][tr + TR * r];
 #pragma unroll
             for (int q = 0; q < RC; ++q) rv[q] = rowbuf[buf][tc + 16 * q];
 #pragma unroll
