@@ -28,6 +28,12 @@
  *              stream) and returns before the GPU finishes.  Calls on one
  *              stream are ordered; calls from several host threads must use
  *              different streams.
+ *   Graphs     the first inversion with a given mode, order, leading
+ *              dimensions, buffers and stream workspace records its launch
+ *              sequence as a HIP graph; later identical calls replay it.  At
+ *              most 64 graphs are kept (the cache is emptied when full, after
+ *              waiting for the device).  The environment variable
+ *              SPIN_NO_GRAPH=1 makes every call launch its kernels directly.
  *   Errors     the return value is an argument or resource status known at
  *              enqueue time: 0 = enqueued, negative = SPIN_E_* (nothing was
  *              enqueued).  The numerical status (a zero or non-finite leaf
