@@ -72,6 +72,27 @@ __device__ inline int group_member(const GroupArgs<N> &g, int bid) {
     return pi;
 }
 
+// Tile (tm, tn) of the t-th workgroup of a problem with tiles_m x tiles_n
+// tiles whose range starts at workgroup tstart. Workgroups are dealt to the
+// eight XCDs round-robin (workgroup b runs on XCD b mod 8), and each XCD has
+// its own L2: when the range and both tile counts are multiples of 8, XCD x
+// gets the contiguous stretch [x T/8, (x+1) T/8) of an order made of 8 x 8
+// tile blocks, so the A rows and B columns it reads stay in its own L2.
+// Otherwise tiles go in plain column-major order. Either way every tile is
+// computed exactly once, with the same arithmetic.
+__device__ inline void tile_coords(int t, int tstart, int tiles_m, int tiles_n, int &tm, int &tn) {
+    if ((tstart & 7) == 0 && (tiles_m & 7) == 0 && (tiles_n & 7) == 0) {
+        const int u = (t & 7) * ((tiles_m * tiles_n) >> 3) + (t >> 3);
+        const int blk = u >> 6, in = u & 63;
+        const int bms = tiles_m >> 3;
+        tm = (blk % bms) * 8 + (in & 7);
+        tn = (blk / bms) * 8 + (in >> 3);
+    } else {
+        tm = t % tiles_m;
+        tn = t / tiles_m;
+    }
+}
+
 template <int BM, int BN, int BK, int WM, int WN, typename T, int NG>
 __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
     constexpr int NT = 256;
@@ -92,8 +113,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
     const int pi = group_member(g, bid);
     const GemmProb P = g.p[pi];
     const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
-    const int t = bid - tstart;
-    const int tm = t % tiles_m, tn = t / tiles_m;
+    int tm, tn;
+    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, tm, tn);
 
     const int M = P.m, N = P.n, K = P.k;
     const int m0 = tm * BM, n0 = tn * BN;
@@ -240,8 +261,8 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
     const int pi = group_member(g, bid);
     const GemmProb P = g.p[pi];
     const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
-    const int t = bid - tstart;
-    const int tm = t % tiles_m, tn = t / tiles_m;
+    int tm, tn;
+    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, tm, tn);
     const int M = P.m, N = P.n, K = P.k;
     const int m0 = tm * BM, n0 = tn * BN;
     const int64_t lda = P.lda, ldb = P.ldb;
@@ -408,8 +429,8 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
     const int pi = group_member(g, bid);
     const GemmProb P = g.p[pi];
     const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
-    const int t = bid - tstart;
-    const int tm = t % tiles_m, tn = t / tiles_m;
+    int tm, tn;
+    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, tm, tn);
     const int M = P.m, N = P.n, K = P.k;
     const int m0 = tm * BM, n0 = tn * BN;
     const float *__restrict__ A = static_cast<const float *>(P.A);
