@@ -170,6 +170,21 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
         if (row >= L || (!WHOLE && k0 > 0 && a.used[row] != 0)) usdm |= 1 << j;
     }
     int bad = 0;
+    // Panels gather the pivot rows of the columns outside the panel during
+    // the steps: thread t < L - nb owns outside column gj, loads its entry in
+    // row p at step c and stores it to Q one step later, when the load has
+    // long completed.  The panel kernel never writes those columns, so the
+    // values are the ones a gather after the last step would read.
+    static_assert(WHOLE || LMAX <= NT, "one gathering thread per outside column");
+    const bool gth = !WHOLE && nb < L && t < L - nb;
+    const int gj = t < k0 ? t : t + nb;
+    const double *gsrc = WHOLE ? nullptr : src + (int64_t)gj * lds;
+    double *gdst = WHOLE ? nullptr : a.Q + (int64_t)gj * nb;
+    double gv = 0.0;
+    // All initial loads complete here (vmcnt(0), the other counters left at
+    // their maximum).  Otherwise the first uses of z inside the loop carry a
+    // wait for every outstanding load, which would include the gathered one.
+    if constexpr (!WHOLE) __builtin_amdgcn_s_waitcnt(0xF70);
     __syncthreads();
 
 #pragma unroll
@@ -254,6 +269,10 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
                 prow_s[c] = p;
             }
             __syncthreads();
+            if (gth) {
+                if (c > 0) gdst[c - 1] = gv;
+                gv = gsrc[p];
+            }
             double f[RR], rv[RC];
 #pragma unroll
             for (int r = 0; r < RR; ++r)
@@ -299,28 +318,7 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
             else if (pivstep[row] >= 0)
                 a.used[row] = 1;
         }
-        if (nb < L) {
-            // rows of Q (the pivot rows) in lane order, NT / NBMAX columns per
-            // pass; every pass's load is issued before the first store
-            constexpr int JS = NT / NBMAX;
-            constexpr int JN = LMAX / JS;
-            static_assert(JN * JS == LMAX, "passes must cover the rows");
-            const int c = t % NBMAX, j0 = t / NBMAX;
-            const int rp = c < nb ? prow_s[c] : 0;
-            const bool cok = c < nb && (unsigned)rp < (unsigned)L;
-            double v[JN];
-#pragma unroll
-            for (int u = 0; u < JN; ++u) {
-                const int j = j0 + u * JS;
-                const bool ok = cok && j < L && (j < k0 || j >= k0 + nb);
-                v[u] = ok ? src[rp + (int64_t)j * lds] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < JN; ++u) {
-                const int j = j0 + u * JS;
-                if (cok && j < L && (j < k0 || j >= k0 + nb)) a.Q[c + (int64_t)j * nb] = v[u];
-            }
-        }
+        if (gth) gdst[nb - 1] = gv;
     }
     if (t == 0 && bad) atomicMin(a.status, a.col0 + k0 + bad);
 }

@@ -50,7 +50,7 @@ def _host(t):
 # m % 4, k % 4 and the leading dimensions decide between the vector and the
 # guarded kernel; the tile count decides between 128, 64 and 32 tiles.
 SHAPES = [(64, 64, 64), (200, 136, 300), (130, 70, 45), (33, 17, 5), (1, 1, 1),
-          (512, 512, 512), (2048, 1536, 96), (2050, 1540, 99)]
+          (512, 512, 512), (2048, 1536, 96), (2050, 1540, 99), (2048, 2048, 64)]
 
 
 @pytest.mark.parametrize("mode", ["bf16", "bf16x3"])

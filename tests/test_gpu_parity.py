@@ -59,6 +59,9 @@ GEMM_CASES = [
     (300, 257, 513, -1.0, 1.0, False, 5),
     (512, 512, 512, -1.0, 0.0, True, 0),
     (1000, 24, 700, 1.0, 0.0, False, 2),
+    # 128-tile kernel: 16 x 16 tiles take the XCD block order, 16 x 12 the plain order
+    (2048, 2048, 64, -1.0, 1.0, False, 0),
+    (2048, 1536, 100, 1.0, 1.0, False, 3),
     (40, 40, 0, -1.0, 1.0, True, 0),
 ]
 
