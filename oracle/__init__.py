@@ -10,6 +10,9 @@ Contents
                          Alg. 1, Sec. 3.1).
   * ``strassen_inv``  -- O2, Strassen's scheme exactly as Alg. 1 lists it
                          (V-form: V = A21 A11^-1 A12 - A22, C22 = -V^-1).
+  * ``strassen_inv_spd`` -- O3, Alg. 1 specialised to symmetric A (the
+                         positive-definite matrices of Sec. 2.1): III = II^T,
+                         so IV = II A12, C12 = C21^T and VII = C12 II.
   * ``gemm``          -- the plain matrix product of ``multiply`` (Sec. 3.3).
   * ``ns_step``       -- one Newton refinement step X + X (I - A X)
                          (Newton iteration as Strassen-inversion stabiliser,
@@ -58,6 +61,8 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_gj_inv.restype = ctypes.c_int
     lib.oracle_strassen_inv.argtypes = [dp, i64, i64, dp, i64, i64]
     lib.oracle_strassen_inv.restype = ctypes.c_int
+    lib.oracle_strassen_inv_spd.argtypes = [dp, i64, i64, dp, i64, i64]
+    lib.oracle_strassen_inv_spd.restype = ctypes.c_int
     lib.oracle_ns_step.argtypes = [dp, i64, i64, dp, i64, dp, i64]
     lib.oracle_ns_step.restype = ctypes.c_int
     lib.oracle_split.argtypes = [i64]
@@ -118,6 +123,17 @@ def strassen_inv(a, leaf: int, lib: ctypes.CDLL | None = None):
     assert a.shape == (n, n)
     x = np.zeros((n, n), dtype=np.float64, order="F")
     info = lib.oracle_strassen_inv(_ptr(a), n, max(n, 1), _ptr(x), max(n, 1), int(leaf))
+    return x, int(info)
+
+
+def strassen_inv_spd(a, leaf: int, lib: ctypes.CDLL | None = None):
+    """O3 (Alg. 1 for symmetric A, four products per node): returns (X, info)."""
+    lib = lib or load()
+    a = _f64(a)
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    x = np.zeros((n, n), dtype=np.float64, order="F")
+    info = lib.oracle_strassen_inv_spd(_ptr(a), n, max(n, 1), _ptr(x), max(n, 1), int(leaf))
     return x, int(info)
 
 

@@ -234,6 +234,77 @@ int oracle_strassen_inv(const double *A, int64_t n, int64_t lda, double *X, int6
     return strassen_rec(A, n, lda, X, ldx, leaf, 0);
 }
 
+/* R (c x r, ldr) = P^T for P (r x c, ldp). */
+static void mat_transpose(const double *P, int64_t ldp, double *R, int64_t ldr, int64_t r, int64_t c)
+{
+    for (int64_t j = 0; j < c; ++j)
+        for (int64_t i = 0; i < r; ++i)
+            AT(R, j, i, ldr) = AT(P, i, j, ldp);
+}
+
+/* O3, Alg. 1 specialised to a symmetric A (the positive-definite matrices the
+ * paper targets, Sec. 2.1).  With A12 = A21^T and every inverse symmetric,
+ * Alg. 1's III = I A12 equals II^T, so
+ *   IV  = A21 III = II A12,
+ *   C12 = III VI  = (VI II)^T = C21^T,
+ *   VII = III C21 = C12 II,
+ * and a node needs four products instead of six.  V-form as in Alg. 1:
+ * V = IV - A22, C22 = -VI.  Both triangles of A are read, so the result is
+ * the SPD specialisation only for an exactly symmetric A.  The temporaries
+ * carry an s suffix (Is = I, IIs = II, ...) to keep them apart from O2's. */
+static int strassen_spd_rec(const double *A, int64_t m, int64_t lda, double *C, int64_t ldc,
+                            int64_t leaf, int64_t col0)
+{
+    if (m <= leaf) {
+        int info = oracle_gj_inv(A, m, lda, C, ldc);
+        return info > 0 ? (int)(info + col0) : info;
+    }
+    const int64_t n1 = oracle_split(m), n2 = m - n1;
+    const double *A11 = &AT(A, 0, 0, lda), *A12 = &AT(A, 0, n1, lda);
+    const double *A21 = &AT(A, n1, 0, lda), *A22 = &AT(A, n1, n1, lda);
+    double *C11 = &AT(C, 0, 0, ldc), *C12 = &AT(C, 0, n1, ldc);
+    double *C21 = &AT(C, n1, 0, ldc), *C22 = &AT(C, n1, n1, ldc);
+
+    double *Is = dalloc(n1, n1), *IIs = dalloc(n2, n1), *IVs = dalloc(n2, n2);
+    double *Vs = dalloc(n2, n2), *VIs = dalloc(n2, n2), *VIIs = dalloc(n1, n1);
+    int info = -1;
+    if (!Is || !IIs || !IVs || !Vs || !VIs || !VIIs)
+        goto done;
+
+    info = strassen_spd_rec(A11, n1, lda, Is, n1, leaf, col0);     /* Is   = A11^-1     */
+    if (info)
+        goto done;
+    oracle_gemm(A21, lda, Is, n1, IIs, n2, n2, n1, n1);            /* IIs  = A21 Is     */
+    oracle_gemm(IIs, n2, A12, lda, IVs, n2, n2, n2, n1);           /* IVs  = IIs A12    */
+    mat_sub(IVs, n2, A22, lda, Vs, n2, n2, n2);                    /* Vs   = IVs - A22  */
+    info = strassen_spd_rec(Vs, n2, n2, VIs, n2, leaf, col0 + n1); /* VIs  = Vs^-1      */
+    if (info)
+        goto done;
+    oracle_gemm(VIs, n2, IIs, n2, C21, ldc, n2, n1, n2);           /* C21  = VIs IIs    */
+    mat_transpose(C21, ldc, C12, ldc, n2, n1);                     /* C12  = C21^T      */
+    oracle_gemm(C12, ldc, IIs, n2, VIIs, n1, n1, n1, n2);          /* VIIs = C12 IIs    */
+    mat_sub(Is, n1, VIIs, n1, C11, ldc, n1, n1);                   /* C11  = Is - VIIs  */
+    mat_neg(VIs, n2, C22, ldc, n2, n2);                            /* C22  = -VIs       */
+done:
+    free(Is);
+    free(IIs);
+    free(IVs);
+    free(Vs);
+    free(VIs);
+    free(VIIs);
+    return info;
+}
+
+int oracle_strassen_inv_spd(const double *A, int64_t n, int64_t lda, double *X, int64_t ldx,
+                            int64_t leaf)
+{
+    if (n <= 0)
+        return 0;
+    if (leaf < 1)
+        return -2;
+    return strassen_spd_rec(A, n, lda, X, ldx, leaf, 0);
+}
+
 /* One refinement step: Xn = X + X (I - A X). */
 int oracle_ns_step(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
                    double *Xn, int64_t ldxn)

@@ -34,6 +34,41 @@ MUTANTS = {
 }
 
 
+# Mistakes planted in O3, the symmetric specialisation.
+SPD_MUTANTS = {
+    "spd_c12_not_transposed": ("mat_transpose(C21, ldc, C12, ldc, n2, n1);",
+                               "mat_copy(C21, ldc, C12, ldc, n1, n2);"),
+    "spd_vii_operand_order": ("oracle_gemm(C12, ldc, IIs, n2, VIIs, n1, n1, n1, n2);",
+                              "oracle_gemm(IIs, n2, C12, ldc, VIIs, n1, n1, n1, n2);"),
+    "spd_iv_uses_a21": ("oracle_gemm(IIs, n2, A12, lda, IVs, n2, n2, n2, n1);",
+                        "oracle_gemm(IIs, n2, A21, lda, IVs, n2, n2, n2, n1);"),
+    "spd_schur_sign": ("mat_sub(IVs, n2, A22, lda, Vs, n2, n2, n2);",
+                       "mat_sub(A22, lda, IVs, n2, Vs, n2, n2, n2);"),
+    "spd_c22_sign": ("mat_neg(VIs, n2, C22, ldc, n2, n2);", "mat_copy(VIs, n2, C22, ldc, n2, n2);"),
+    "spd_c11_dropped_term": ("mat_sub(Is, n1, VIIs, n1, C11, ldc, n1, n1);",
+                             "mat_copy(Is, n1, C11, ldc, n1, n1);"),
+    "spd_second_leaf_offset": ("leaf, col0 + n1); /* VIs", "leaf, col0); /* VIs"),
+}
+
+
+def _spd_pins_pass(lib) -> bool:
+    """A compact set of the pins from test_oracle_spd; True iff all hold."""
+    ok = True
+    A = W.spd_unimodular(32, seed=40)
+    X, info = oracle.strassen_inv_spd(A, 8, lib)
+    ok &= info == 0 and np.array_equal(X, to_float(exact_inverse(A)))
+    G = W.spd_gram(200, 2)
+    X, info = oracle.strassen_inv_spd(G, 32, lib)
+    ref = np.linalg.inv(G)
+    ok &= info == 0 and np.linalg.norm(X - ref) / np.linalg.norm(ref) < 1e-12
+    Z = W.spd_gram(64, 8)
+    Z[:, 40] = 0.0
+    Z[40, :] = 0.0
+    _, info = oracle.strassen_inv_spd(Z, 32, lib)
+    ok &= info == 41
+    return bool(ok)
+
+
 def _pins_pass(lib) -> bool:
     """A compact set of the pins from test_oracle_pins; True iff all hold."""
     ok = True
@@ -81,7 +116,9 @@ def test_unmutated_passes(tmp_path):
     path.write_text(open(SRC).read())
     out = str(tmp_path / "libsame.so")
     oracle.build(str(path), out)
-    assert _pins_pass(oracle.load(out))
+    lib = oracle.load(out)
+    assert _pins_pass(lib)
+    assert _spd_pins_pass(lib)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -89,3 +126,10 @@ def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     lib = _build_variant(tmp_path, name, old, new)
     assert not _pins_pass(lib), f"mutant {name} survived the oracle pins"
+
+
+@pytest.mark.parametrize("name", sorted(SPD_MUTANTS))
+def test_spd_mutant_is_caught(tmp_path, name):
+    old, new = SPD_MUTANTS[name]
+    lib = _build_variant(tmp_path, name, old, new)
+    assert not _spd_pins_pass(lib), f"mutant {name} survived the O3 pins"

@@ -136,6 +136,20 @@ def unimodular_bidiag(n: int, seed: int) -> np.ndarray:
     return _fortran(lo @ up)
 
 
+def spd_unimodular(n: int, seed: int) -> np.ndarray:
+    """``L L^T`` with ``L`` unit lower bidiagonal, off-diagonals +-1.
+
+    Symmetric positive definite and tridiagonal, with determinant 1 and an
+    integer inverse; every leading block is of the same form, so its
+    Schur complements are too.
+    """
+    g = rng(seed)
+    lo = np.eye(n)
+    if n > 1:
+        lo[np.arange(1, n), np.arange(n - 1)] = g.choice([-1.0, 1.0], size=n - 1)
+    return _fortran(lo @ lo.T)
+
+
 def permutation(n: int, seed: int) -> np.ndarray:
     """A random permutation matrix."""
     g = rng(seed)
