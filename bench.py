@@ -15,7 +15,13 @@ Prints one JSON line.  Extra fields:
                   algorithmic flops per launch / average launch duration,
                   against the FP64 MFMA peak;
   cpu_baseline -- the CPU oracle (literal Alg. 1 recursion, OpenMP) timed on a
-                  bounded sample of the same workload on the host cores.
+                  bounded sample of the same workload on the host cores;
+  spd_variant  -- spin_invert_spd (four products and a transpose per node) on
+                  the same symmetric matrix, timed the same way, beside the
+                  plain method (which alone gives `value`).
+
+With --spd the timed step itself is spin_invert_spd (for profiling it); the
+default step is always the plain method of Alg. 1.
 """
 from __future__ import annotations
 
@@ -43,6 +49,8 @@ def parse():
     p.add_argument("--leaf", type=int, default=256)
     p.add_argument("--kind", default="spd", choices=["spd", "dd", "spdk"])
     p.add_argument("--mode", default="fp64", choices=["fp64", "fp32"])
+    p.add_argument("--spd", action="store_true",
+                   help="time spin_invert_spd as the step (symmetric inputs only)")
     p.add_argument("--ns-steps", type=int, default=2)
     p.add_argument("--seed", type=int, default=None)
     p.add_argument("--no-cpu", action="store_true")
@@ -168,6 +176,37 @@ def mixed_vs_fp64(n: int, leaf: int, reps: int):
     del dA, dX
     spin.release()
     torch.cuda.empty_cache()
+    return out
+
+
+def spd_variant(dA, n: int, leaf: int, steps: int, warmup: int, plain_ms: float):
+    """spin_invert_spd on the same symmetric matrix: the same timing as the
+    main step, its residual, and the schedule's own flop count."""
+    import torch
+    import paper_1801_04723_amd as spin
+    dX = torch.empty_like(dA)
+    for _ in range(warmup):
+        spin.invert_spd(dA, leaf=leaf, out=dX)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        spin.invert_spd(dA, leaf=leaf, out=dX)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    _, sched_flops = spin.plan_describe(n, leaf, spd=True)
+    out = {
+        "ms": round(ms, 4),
+        "time_vs_plain": round(ms / plain_ms, 4),
+        "tflops_2n3": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 3),
+        "schedule_flops": sched_flops,
+        "schedule_tflops": round(sched_flops / (ms * 1e-3) / 1e12, 3),
+        "rho": spin.residual(dA, dX),
+        "status": spin.info(),
+    }
+    del dX
     return out
 
 
@@ -297,8 +336,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.spd and (args.mode != "fp64" or args.kind == "dd"):
+        raise SystemExit("--spd needs --mode fp64 and a symmetric --kind (spd or spdk)")
+
     def step():
-        if args.mode == "fp64":
+        if args.spd:
+            spin.invert_spd(dA, leaf=leaf, out=dX)
+        elif args.mode == "fp64":
             spin.invert(dA, leaf=leaf, out=dX)
         else:
             spin.invert_mixed(dA, leaf=leaf, mode="fp32", ns_steps=args.ns_steps, out=dX)
@@ -335,7 +379,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{desc}, n={n}, leaf={leaf}, {args.mode}"
-                        + (f", {args.ns_steps} Newton steps" if args.mode != "fp64" else ""),
+                        + (f", {args.ns_steps} Newton steps" if args.mode != "fp64" else "")
+                        + (", symmetric variant (spin_invert_spd)" if args.spd else ""),
             "n": n, "leaf": leaf, "mode": args.mode,
             "depth": max(0, (n // leaf).bit_length() - 1) if n > leaf else 0,
         },
@@ -357,6 +402,8 @@ def main():
         out["kernel_breakdown"] = breakdown
     else:
         out["roofline"] = None
+    if args.mode == "fp64" and not args.spd and args.kind != "dd":
+        out["spd_variant"] = spd_variant(dA, n, leaf, args.steps, args.warmup, ms)
     if args.serve_seconds > 0:
         out["serving"] = serving(args.serve_rate, args.serve_seconds)
     if args.mixed_n > 0:

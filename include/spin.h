@@ -95,6 +95,24 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
 int spin_invert(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
                 int64_t leaf, spin_stream_t stream);
 
+/* ---- FP64 inversion of a symmetric matrix --------------------------------- */
+/* Ainv := A^-1 for an exactly symmetric A (the positive-definite matrices the
+ * paper targets, Sec. 2.1), Alg. 1 specialised: every block the recursion
+ * inverts is then symmetric, so III = I A12 = II^T, and a node needs four
+ * products and one transpose instead of six products:
+ *   II = A21 I,  S = A22 - II A12,  C22 = S^-1,  C21 = -C22 II,
+ *   C12 = C21^T,  C11 = I - C12 II.
+ * Arguments, layout, ownership, workspace (spin_workspace_bytes with
+ * SPIN_FP64 covers it) and status reporting are those of spin_invert.  Both
+ * triangles of A are read; for a matrix that is not exactly symmetric the
+ * result is unspecified.  Ainv's off-diagonal blocks are exact transposes of
+ * each other at every level.  Accuracy: C12 = C21^T uses the symmetry of
+ * the computed inverses, which holds only to about kappa(A) u, so the
+ * residual grows like kappa(A) u (rho about 3e-13 at kappa = 1e4), where
+ * spin_invert stays near u. */
+int spin_invert_spd(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                    int64_t leaf, spin_stream_t stream);
+
 /* ---- mixed-precision inversion with Newton refinement --------------------- */
 typedef struct spin_report {
     double rho_before;   /* |A X0 - I|_F / (|A|_F |X0|_F) of the unrefined inverse */
@@ -201,7 +219,8 @@ size_t spin_server_request_bytes(int64_t n, int64_t leaf, int mode);
  * Schur complement S = A22 - A21 A11^-1 A12 = -V is formed and inverted
  * directly, so C22 = S^-1 and C12 = -III C22, C21 = -C22 II). */
 typedef struct spin_plan_op {
-    int kind;        /* 0 = group of block products, 1 = leaf inversion        */
+    int kind;        /* 0 = group of block products, 1 = leaf inversion,
+                        2 = transpose (spin_plan_describe_spd only)            */
     int count;       /* products in the group (1 or 2); 1 for a leaf          */
     int level;       /* recursion depth of the node that issues it            */
     int pad_;
@@ -212,6 +231,7 @@ typedef struct spin_plan_op {
     int64_t a_ld[2], b_ld[2], c_ld[2], d_ld[2];
     double alpha[2], beta[2];
     /* leaf: out (order L, at d_*[0]) := in^-1 (at a_*[0]); col0 = global column */
+    /* transpose: d (n[0] x m[0], at d_*[0]) := a (m[0] x n[0], at a_*[0])^T      */
     int64_t leaf_order, col0;
 } spin_plan_op;
 
@@ -222,6 +242,10 @@ typedef struct spin_plan_op {
  * schedule's arithmetic count: 2 m n k per product, 2 L^3 per leaf. */
 int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
                            spin_plan_op *ops, int64_t cap, double *flops);
+/* The same for the schedule of spin_invert_spd (kinds 0, 1 and 2); its
+ * workspace is at most spin_plan_ws_elems(n, leaf) elements. */
+int64_t spin_plan_describe_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
+                               spin_plan_op *ops, int64_t cap, double *flops);
 int64_t spin_plan_ws_elems(int64_t n, int64_t leaf);
 
 /* ---- per-kernel timing (for profiling; forces eager launches) ------------- */

@@ -120,6 +120,10 @@ def lib() -> ctypes.CDLL:
         L.spin_plan_describe.argtypes = [_i64, _i64, _i64, _i64, ctypes.POINTER(PlanOp), _i64,
                                          ctypes.POINTER(ctypes.c_double)]
         L.spin_plan_describe.restype = _i64
+        L.spin_plan_describe_spd.argtypes = L.spin_plan_describe.argtypes
+        L.spin_plan_describe_spd.restype = _i64
+        L.spin_invert_spd.argtypes = L.spin_invert.argtypes
+        L.spin_invert_spd.restype = ctypes.c_int
         L.spin_plan_ws_elems.argtypes = [_i64, _i64]
         L.spin_plan_ws_elems.restype = _i64
         L.spin_trace_enable.argtypes = [ctypes.c_int]
@@ -171,17 +175,20 @@ def plan_ws_elems(n: int, leaf: int) -> int:
     return int(lib().spin_plan_ws_elems(int(n), int(leaf)))
 
 
-def plan_describe(n: int, leaf: int, lda: int | None = None, ldx: int | None = None):
-    """The recursion schedule as a list of dicts, plus its flop count."""
+def plan_describe(n: int, leaf: int, lda: int | None = None, ldx: int | None = None,
+                  spd: bool = False):
+    """The recursion schedule (of spin_invert_spd when spd=True) as a list of
+    dicts, plus its flop count."""
     lda = n if lda is None else lda
     ldx = n if ldx is None else ldx
     L = lib()
+    fn = L.spin_plan_describe_spd if spd else L.spin_plan_describe
     fl = ctypes.c_double(0)
-    cnt = L.spin_plan_describe(n, lda, ldx, leaf, None, 0, ctypes.byref(fl))
+    cnt = fn(n, lda, ldx, leaf, None, 0, ctypes.byref(fl))
     if cnt < 0:
         raise SpinError(int(cnt), "spin_plan_describe")
     arr = (PlanOp * max(int(cnt), 1))()
-    L.spin_plan_describe(n, lda, ldx, leaf, arr, cnt, ctypes.byref(fl))
+    fn(n, lda, ldx, leaf, arr, cnt, ctypes.byref(fl))
     ops = []
     for o in arr[: int(cnt)]:
         if o.kind == 0:
@@ -194,6 +201,10 @@ def plan_describe(n: int, leaf: int, lda: int | None = None, ldx: int | None = N
                                   d=(o.d_buf[q], o.d_off[q], o.d_ld[q]),
                                   alpha=o.alpha[q], beta=o.beta[q]))
             ops.append(dict(kind="products", level=o.level, products=prods))
+        elif o.kind == 2:
+            ops.append(dict(kind="transpose", level=o.level, m=o.m[0], n=o.n[0],
+                            src=(o.a_buf[0], o.a_off[0], o.a_ld[0]),
+                            dst=(o.d_buf[0], o.d_off[0], o.d_ld[0])))
         else:
             ops.append(dict(kind="leaf", level=o.level, L=o.leaf_order, col0=o.col0,
                             src=(o.a_buf[0], o.a_off[0], o.a_ld[0]),
@@ -260,6 +271,23 @@ def invert(a, leaf: int, out=None, stream=None):
     rc = lib().spin_invert(a.data_ptr(), a.shape[0], lda, out.data_ptr(), ldx, int(leaf), _stream(stream))
     if rc != 0:
         raise SpinError(rc, "spin_invert")
+    return out
+
+
+def invert_spd(a, leaf: int, out=None, stream=None):
+    """A^-1 for an exactly symmetric A by the four-product FP64 recursion
+    (asynchronous on `stream`)."""
+    _check_square(a)
+    lda, order = _layout(a)
+    if out is None:
+        out = _empty_like_layout(a, order)
+    ldx, order_x = _layout(out)
+    if order_x != order:
+        raise ValueError("output must have the same memory order as the input")
+    rc = lib().spin_invert_spd(a.data_ptr(), a.shape[0], lda, out.data_ptr(), ldx, int(leaf),
+                               _stream(stream))
+    if rc != 0:
+        raise SpinError(rc, "spin_invert_spd")
     return out
 
 

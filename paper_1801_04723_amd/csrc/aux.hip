@@ -1,5 +1,5 @@
 // Auxiliary bandwidth-bound kernels: status reset, precision conversion,
-// copies and deterministic Frobenius-norm reductions.
+// copies, transposes and deterministic Frobenius-norm reductions.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -24,6 +24,28 @@ __global__ void __launch_bounds__(256)
         for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m;
              i += (int64_t)gridDim.x * 256)
             dst[i + j * ldd] = (D)src[i + j * lds];
+}
+
+// dst (n x m, ldd) = src (m x n, lds)^T.  A workgroup moves one 64 x 64 tile
+// through LDS: it reads down the source columns and writes down the
+// destination columns, so both sides coalesce.  The row pitch of 65 doubles
+// spreads the transposed LDS reads over the banks.
+constexpr int kTT = 64;
+__global__ void __launch_bounds__(256)
+    k_transpose(const double *__restrict__ src, int64_t lds, double *__restrict__ dst, int64_t ldd,
+                int64_t m, int64_t n) {
+    __shared__ double tile[kTT][kTT + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * kTT, j0 = (int64_t)blockIdx.y * kTT;
+    const int tx = threadIdx.x & (kTT - 1), ty = threadIdx.x / kTT;
+    for (int jj = ty; jj < kTT; jj += 256 / kTT) {
+        const int64_t i = i0 + tx, j = j0 + jj;
+        if (i < m && j < n) tile[jj][tx] = src[i + j * lds];
+    }
+    __syncthreads();
+    for (int ii = ty; ii < kTT; ii += 256 / kTT) {
+        const int64_t r = j0 + tx, c = i0 + ii;  // dst row = src column
+        if (r < n && c < m) dst[r + c * ldd] = tile[tx][ii];
+    }
 }
 
 // Per-block partial sums of squares over whole columns (fixed assignment of
@@ -97,6 +119,16 @@ hipError_t cast_f32_to_f64(const float *src, int64_t lds, double *dst, int64_t l
 hipError_t copy_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
                     int64_t n, hipStream_t s) {
     return convert<double, double>(src, lds, dst, ldd, m, n, s);
+}
+
+hipError_t transpose_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
+                         int64_t n, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int64_t gx = (m + kTT - 1) / kTT, gy = (n + kTT - 1) / kTT;
+    if (gx > INT_MAX || gy > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, src, lds, dst,
+                       ldd, m, n);
+    return hipGetLastError();
 }
 
 hipError_t ns_check(const double *norms, int j, int *status, hipStream_t s) {

@@ -100,7 +100,64 @@ void plan_node(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level, in
     push_products(P, level, PGemm{III, C21, C11, C11, n1, n1, n2, -1.0, 1.0, 0}, nullptr);
 }
 
+// Alg. 1 for a symmetric A (the positive-definite matrices of Sec. 2.1),
+// S-form.  Every block the recursion inverts is then symmetric, so III =
+// I A12 = II^T and
+//   S   = A22 - A21 III = A22 - II A12,
+//   C12 = -III C22      = C21^T,
+//   C11 = I - III C21   = I - C12 II.
+// A node costs four products (II, S, C21, C11) and one transpose instead of
+// six products.  Only the transpose relies on symmetry; S and C11 are the
+// same products regrouped.  II (n2 x n1) and S live in the workspace.
+void plan_node_spd(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level, int64_t col0) {
+    if (m <= P.leaf) {
+        plan_node(P, in, out, m, wsoff, level, col0);
+        return;
+    }
+    const int64_t n1 = split_order(m), n2 = m - n1;
+    const Ref A21 = sub(in, n1, 0), A12 = sub(in, 0, n1), A22 = sub(in, n1, n1);
+    const Ref C11 = sub(out, 0, 0), C21 = sub(out, n1, 0), C12 = sub(out, 0, n1),
+              C22 = sub(out, n1, n1);
+    // I = A11^-1, stored in the C11 view
+    plan_node_spd(P, sub(in, 0, 0), C11, n1, wsoff, level + 1, col0);
+    const Ref II{BUF_WS, wsoff, n2};
+    const Ref S{BUF_WS, wsoff + n2 * n1, n2};
+    const int64_t next = wsoff + n2 * n1 + n2 * n2;
+    P.ws_elems = std::max(P.ws_elems, next);
+    const Ref none{BUF_WS, 0, 1};
+    // II = A21 I
+    push_products(P, level, PGemm{A21, C11, none, II, n2, n1, n1, 1.0, 0.0, 0}, nullptr);
+    // S = A22 - II A12  (= A22 - A21 III = -V)
+    push_products(P, level, PGemm{II, A12, A22, S, n2, n2, n1, -1.0, 1.0, 0}, nullptr);
+    // C22 = S^-1  (= -VI)
+    plan_node_spd(P, S, C22, n2, next, level + 1, col0 + n1);
+    // C21 = -C22 II  (= VI II)
+    push_products(P, level, PGemm{C22, II, none, C21, n2, n1, n2, -1.0, 0.0, 0}, nullptr);
+    // C12 = C21^T  (= III VI)
+    POp t{};
+    t.kind = 2;
+    t.count = 1;
+    t.level = level;
+    t.in = C21;
+    t.out = C12;
+    t.tm = n2;
+    t.tn = n1;
+    P.ops.push_back(t);
+    // C11 = I - C12 II  (= I - III C21), in place on the C11 view
+    push_products(P, level, PGemm{C12, II, C11, C11, n1, n1, n2, -1.0, 1.0, 0}, nullptr);
+}
+
 }  // namespace
+
+Plan make_plan_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf) {
+    Plan P;
+    P.n = n;
+    P.lda = lda;
+    P.ldx = ldx;
+    P.leaf = leaf;
+    plan_node_spd(P, Ref{BUF_A, 0, lda}, Ref{BUF_X, 0, ldx}, n, 0, 0, 0);
+    return P;
+}
 
 Plan make_plan(int64_t n, int64_t lda, int64_t ldx, int64_t leaf) {
     Plan P;
@@ -269,6 +326,15 @@ hipError_t run_plan(const Plan &P, const Exec &E) {
             hipError_t e = gemm_launch(pr, op.count, E.gdt, E.s, &li);
             if (tr) trace_cb(&ctx, li, 1);
             if (e != hipSuccess) return e;
+        } else if (op.kind == 2) {
+            if (E.dt != kF64) return hipErrorInvalidValue;
+            LaunchInfo li{"transpose", 0.0, 16.0 * (double)op.tm * (double)op.tn};
+            if (tr) trace_cb(&ctx, li, 0);
+            hipError_t e = transpose_f64(static_cast<const double *>(at(E, op.in)), op.in.ld,
+                                         static_cast<double *>(at(E, op.out)), op.out.ld, op.tm,
+                                         op.tn, E.s);
+            if (tr) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
         } else {
             hipError_t e = leaf_launch(at(E, op.in), E.dt, op.in.ld, at(E, op.out), E.dt,
                                        op.out.ld, op.L, op.col0, E.status, E.leaf_scratch, E.s,
@@ -375,6 +441,31 @@ int spin_invert(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t l
         return run_plan(P, Eq);
     };
     return run_maybe_graph(std::make_tuple(0, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
+                                           (void *)w->base, 0),
+                           s, body);
+}
+
+int spin_invert_spd(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                    int64_t leaf, spin_stream_t stream) {
+    int rc = validate(A, n, lda, Ainv, ldx, leaf);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan P = make_plan_spd(n, lda, ldx, leaf);
+    Layout L = layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf);
+    Workspace *w = nullptr;
+    rc = ws_acquire(s, L.total, &w);
+    if (rc) return rc;
+    Exec E{s, {(char *)A, (char *)Ainv, w->base + L.rec_off}, 8, kF64, status_ptr(w),
+           w->base + L.leaf_off};
+    auto body = [&](hipStream_t qs) -> hipError_t {
+        Exec Eq = E;
+        Eq.s = qs;
+        hipError_t e = status_reset(Eq.status, 2, qs);
+        if (e != hipSuccess) return e;
+        return run_plan(P, Eq);
+    };
+    return run_maybe_graph(std::make_tuple(2, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
                                            (void *)w->base, 0),
                            s, body);
 }
@@ -594,13 +685,10 @@ void spin_release(void) {
     g_ws.clear();
 }
 
-int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf, spin_plan_op *ops,
-                           int64_t cap, double *flops) {
-    if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
-    if (lda < n || ldx < n) return SPIN_E_LD;
-    if (leaf < 1 || leaf > SPIN_MAX_LEAF) return SPIN_E_LEAF;
-    if (cap > 0 && !ops) return SPIN_E_NULL;
-    Plan P = make_plan(n, lda, ldx, leaf);
+}  // extern "C"
+
+namespace {
+int64_t describe_plan(const Plan &P, spin_plan_op *ops, int64_t cap, double *flops) {
     if (flops) *flops = P.flops;
     const int64_t cnt = (int64_t)P.ops.size();
     for (int64_t i = 0; i < cnt && i < cap; ++i) {
@@ -631,6 +719,15 @@ int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf, sp
                 o.alpha[q] = g.alpha;
                 o.beta[q] = g.beta;
             }
+        } else if (op.kind == 2) {
+            o.m[0] = op.tm;
+            o.n[0] = op.tn;
+            o.a_buf[0] = op.in.buf;
+            o.a_off[0] = op.in.off;
+            o.a_ld[0] = op.in.ld;
+            o.d_buf[0] = op.out.buf;
+            o.d_off[0] = op.out.off;
+            o.d_ld[0] = op.out.ld;
         } else {
             o.a_buf[0] = op.in.buf;
             o.a_off[0] = op.in.off;
@@ -644,6 +741,28 @@ int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf, sp
         ops[i] = o;
     }
     return cnt;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf, spin_plan_op *ops,
+                           int64_t cap, double *flops) {
+    if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
+    if (lda < n || ldx < n) return SPIN_E_LD;
+    if (leaf < 1 || leaf > SPIN_MAX_LEAF) return SPIN_E_LEAF;
+    if (cap > 0 && !ops) return SPIN_E_NULL;
+    return describe_plan(make_plan(n, lda, ldx, leaf), ops, cap, flops);
+}
+
+int64_t spin_plan_describe_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
+                               spin_plan_op *ops, int64_t cap, double *flops) {
+    if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
+    if (lda < n || ldx < n) return SPIN_E_LD;
+    if (leaf < 1 || leaf > SPIN_MAX_LEAF) return SPIN_E_LEAF;
+    if (cap > 0 && !ops) return SPIN_E_NULL;
+    return describe_plan(make_plan_spd(n, lda, ldx, leaf), ops, cap, flops);
 }
 
 int64_t spin_plan_ws_elems(int64_t n, int64_t leaf) {

@@ -93,6 +93,9 @@ hipError_t cast_f32_to_f64(const float *src, int64_t lds, double *dst, int64_t l
                            int64_t n, hipStream_t s);
 hipError_t copy_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
                     int64_t n, hipStream_t s);
+// dst (n x m, ldd) = src (m x n, lds)^T; the views must not overlap.
+hipError_t transpose_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
+                         int64_t n, hipStream_t s);
 // Sum of squares of an (m x n) FP64 view, deterministic two-pass reduction:
 // partials (>= frob_partials_count(m, n) doubles) then one block writes *out.
 int frob_partials_count(int64_t m, int64_t n);

@@ -28,7 +28,8 @@ struct PGemm {
     int add_identity;
 };
 
-// One step: a group of independent products (kind 0) or a leaf (kind 1).
+// One step: a group of independent products (kind 0), a leaf (kind 1) or a
+// transpose (kind 2: out (tn x tm) := in (tm x tn)^T).
 struct POp {
     int kind;
     int count;
@@ -36,6 +37,7 @@ struct POp {
     PGemm g[2];
     Ref in, out;
     int64_t L, col0;
+    int64_t tm, tn;
 };
 
 struct Plan {
@@ -82,5 +84,7 @@ GemmProb make_prob(char *const base[3], size_t es, const PGemm &g);
 int64_t split_order(int64_t m);
 // Depth-first S-form schedule of Alg. 1 for an order-n matrix.
 Plan make_plan(int64_t n, int64_t lda, int64_t ldx, int64_t leaf);
+// The same for a symmetric matrix: four products and one transpose per node.
+Plan make_plan_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf);
 
 }  // namespace spin

@@ -126,10 +126,10 @@ def test_split_rule_matches_oracle(m):
     assert n1 == oracle.split(m)
 
 
-def _run_schedule_on_cpu(A, leaf):
+def _run_schedule_on_cpu(A, leaf, spd=False):
     """Replay the library's schedule with the oracle's GEMM and GJ."""
     n = A.shape[0]
-    ops, _ = S.plan_describe(n, leaf)
+    ops, _ = S.plan_describe(n, leaf, spd=spd)
     bufs = [np.asfortranarray(A).ravel(order="F").copy(),
             np.zeros(n * n), np.zeros(max(S.plan_ws_elems(n, leaf), 1))]
 
@@ -146,6 +146,9 @@ def _run_schedule_on_cpu(A, leaf):
             assert info == 0
             dst = view(o["dst"], L, L)
             dst[...] = x
+        elif o["kind"] == "transpose":
+            src = np.array(view(o["src"], o["m"], o["n"]))
+            view(o["dst"], o["n"], o["m"])[...] = src.T
         else:
             results = []
             for p in o["products"]:
@@ -169,6 +172,72 @@ def test_schedule_replay_equals_oracle_bitwise(gen, n, leaf):
     ref, info = oracle.strassen_inv(A, leaf)
     assert info == 0
     assert np.array_equal(X, ref)
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (128, 16), (200, 32), (300, 64), (130, 64), (64, 64)])
+def test_spd_schedule_replay_equals_oracle_bitwise(n, leaf):
+    """The four-product schedule of spin_invert_spd, replayed with the oracle's
+    product and leaf routines, is O3 bit for bit (S-form against V-form)."""
+    A = W.spd_gram(n, 2)
+    X = _run_schedule_on_cpu(A, leaf, spd=True)
+    ref, info = oracle.strassen_inv_spd(A, leaf)
+    assert info == 0
+    assert np.array_equal(X, ref)
+
+
+def _spd_flops(m, leaf):
+    """Direct sum over the recursion: 2 L^3 per leaf; per node II (2 n2 n1 n1),
+    S (2 n2 n2 n1), C21 (2 n2 n1 n2) and C11 (2 n1 n1 n2)."""
+    if m <= leaf:
+        return 2 * m ** 3
+    n1 = oracle.split(m)
+    n2 = m - n1
+    return (_spd_flops(n1, leaf) + _spd_flops(n2, leaf)
+            + 2 * n2 * n1 * n1 + 2 * n2 * n2 * n1 + 2 * n2 * n1 * n2 + 2 * n1 * n1 * n2)
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (8192, 256), (16384, 128), (300, 64), (4160, 128), (1, 1)])
+def test_spd_plan_structure(n, leaf):
+    ops, fl = S.plan_describe(n, leaf, spd=True)
+    plain, fl_plain = S.plan_describe(n, leaf)
+    assert fl == _spd_flops(n, leaf)
+    leaves = [o for o in ops if o["kind"] == "leaf"]
+    assert [(o["L"], o["col0"]) for o in leaves] == [(o["L"], o["col0"]) for o in plain if o["kind"] == "leaf"]
+    internal = sum(1 for o in plain if o["kind"] == "products") // 4
+    assert sum(1 for o in ops if o["kind"] == "transpose") == internal
+    prods = [o for o in ops if o["kind"] == "products"]
+    assert len(prods) == 4 * internal and all(len(o["products"]) == 1 for o in prods)
+    if n % leaf == 0 and (n // leaf) & (n // leaf - 1) == 0:
+        d = (n // leaf).bit_length() - 1
+        # 8 h^3 per node instead of 12 h^3: levels sum to (4/3)(1 - 4^-d) n^3
+        assert abs(fl - (4 / 3 * (1 - 4.0 ** -d) * n ** 3 + 2 * n ** 3 / 4 ** d)) <= 1e-9 * fl
+        assert fl_plain == 2 * n ** 3
+    for o in ops:
+        if o["kind"] == "transpose":
+            # C12 (n1 x n2) := C21 (n2 x n1)^T, both in the output
+            assert o["src"][0] == 1 and o["dst"][0] == 1 and o["m"] <= o["n"]
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (8192, 256), (300, 64), (100, 7)])
+def test_spd_workspace_within_plain(n, leaf):
+    """II and S per node: the SPD schedule never addresses more workspace than
+    spin_plan_ws_elems (the plain schedule's) provides."""
+    ops, _ = S.plan_describe(n, leaf, spd=True)
+    ws = S.plan_ws_elems(n, leaf)
+    top = 0
+    for o in ops:
+        refs = []
+        if o["kind"] == "products":
+            for p in o["products"]:
+                refs += [(p["a"], p["m"], p["k"]), (p["b"], p["k"], p["n"]), (p["d"], p["m"], p["n"])]
+                if p["beta"] != 0.0:
+                    refs.append((p["c"], p["m"], p["n"]))
+        elif o["kind"] == "leaf":
+            refs += [(o["src"], o["L"], o["L"]), (o["dst"], o["L"], o["L"])]
+        for (buf, off, ld), r, c in refs:
+            if buf == 2:
+                top = max(top, off + (c - 1) * ld + r)
+    assert top <= ws
 
 
 # ------------------------------------------------------- server admission (CPU)
