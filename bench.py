@@ -65,6 +65,9 @@ def parse():
     p.add_argument("--mixed-reps", type=int, default=2)
     p.add_argument("--gemm-sweep", action="store_true",
                    help="only time spin_gemm alone (FP64, FP32, BF16, bf16x3; h = 2048, 4096, 8192) and exit")
+    p.add_argument("--cost-model", action="store_true",
+                   help="only calibrate the recursion cost model, predict the leaf sweep at n = 16384 "
+                        "(and n = 8192, leaf 256), time the same inversions and exit")
     p.add_argument("--calib-copy", action="store_true",
                    help="run one 512 MiB device-to-device copy first (HBM counter calibration)")
     return p.parse_args()
@@ -261,6 +264,40 @@ def roofline_from_trace(recs, n_steps: int):
     }, breakdown
 
 
+def cost_model_run():
+    """Calibrate the cost model (isolated leaves, nodes and products), then
+    predict and time the leaf sweep of U(-1,1) + n I at n = 16384 and the
+    n = 8192, leaf 256 step."""
+    import torch
+    import paper_1801_04723_amd as spin
+    from paper_1801_04723_amd import costmodel as C
+    import workloads as W
+    t0 = time.perf_counter()
+    rates = C.calibrate()
+    print(f"calibrated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    rows = []
+    for n, leaf in [(16384, L) for L in (64, 128, 256, 512, 1024, 2048)] + [(8192, 256)]:
+        A = W.torch_diag_dominant(n, seed=3)
+        X = torch.empty_like(A)
+        ms = C._time_ms(lambda: spin.invert(A, leaf=leaf, out=X), reps=3, warm=1)
+        p = C.predict(n, leaf, rates)
+        rows.append({"n": n, "leaf": leaf, "measured_ms": round(ms, 3), "predicted_ms": round(p["ms"], 3),
+                     "leaf_term_ms": round(p["leaf_ms"], 3), "node_term_ms": round(p["node_ms"], 3),
+                     "rel_error": round((p["ms"] - ms) / ms, 4), "leaves": p["leaves"], "nodes": p["nodes"]})
+        print(f"n={n} leaf={leaf}: measured {ms:.2f} ms, predicted {p['ms']:.2f} ms", file=sys.stderr, flush=True)
+        del A, X
+        spin.release()
+        torch.cuda.empty_cache()
+    sweep = [r for r in rows if r["n"] == 16384]
+    return {
+        "leaf_ms": {str(k): round(v, 5) for k, v in sorted(rates.leaf_ms.items())},
+        "node_ms": {str(k): round(v, 5) for k, v in sorted(rates.node_ms.items())},
+        "cases": rows,
+        "best_leaf_predicted": C.best_leaf(16384, rates, candidates=(64, 128, 256, 512, 1024, 2048)),
+        "best_leaf_measured": min(sweep, key=lambda r: r["measured_ms"])["leaf"],
+    }
+
+
 def gemm_sweep():
     """Standalone block products D = A B (h x h x h, column-major, ld h) in each
     flavour: mean of 20 back-to-back calls after 3 warm-ups, HIP events on the
@@ -318,6 +355,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.gemm_sweep:
         print(json.dumps({"gemm_sweep": gemm_sweep()}), flush=True)
+        return
+    if args.cost_model:
+        print(json.dumps(finite_json({"cost_model": cost_model_run()})), flush=True)
         return
     dev = torch.device("cuda:0")
     seed = args.seed if args.seed is not None else {"spd": 2, "dd": 3, "spdk": 4}[args.kind]
