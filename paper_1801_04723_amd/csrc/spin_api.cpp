@@ -12,7 +12,9 @@
 //       C12 = -III C22 = III VI and C21 = -C22 II = VI II;
 //   locInverse (Alg. 2, leaf case) -> the leaf Gauss-Jordan kernels.
 // Every internal node issues four launches: {II, III} grouped, S, {C12, C21}
-// grouped, and C11 = C11 - III C21 in place.
+// grouped, and C11 = C11 - III C21 in place.  The schedule for symmetric
+// matrices (spin_invert_spd) issues five: II, S, C21, the transpose
+// C12 = C21^T, and C11 = C11 - C12 II.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
