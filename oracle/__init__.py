@@ -12,7 +12,8 @@ Contents
                          (V-form: V = A21 A11^-1 A12 - A22, C22 = -V^-1).
   * ``strassen_inv_spd`` -- O3, Alg. 1 specialised to symmetric A (the
                          positive-definite matrices of Sec. 2.1): III = II^T,
-                         so IV = II A12, C12 = C21^T and VII = C12 II.
+                         so IV = II A12, C12 = C21^T and VII = C12 II; V and
+                         C11 keep their lower triangles, mirrored.
   * ``gemm``          -- the plain matrix product of ``multiply`` (Sec. 3.3).
   * ``ns_step``       -- one Newton refinement step X + X (I - A X)
                          (Newton iteration as Strassen-inversion stabiliser,

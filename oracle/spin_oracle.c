@@ -242,16 +242,29 @@ static void mat_transpose(const double *P, int64_t ldp, double *R, int64_t ldr, 
             AT(R, j, i, ldr) = AT(P, i, j, ldp);
 }
 
+/* Lower triangle mirrored onto the upper one: P[i][j] = P[j][i] for j > i. */
+static void mat_mirror_lower(double *P, int64_t ldp, int64_t m)
+{
+    for (int64_t j = 1; j < m; ++j)
+        for (int64_t i = 0; i < j; ++i)
+            AT(P, i, j, ldp) = AT(P, j, i, ldp);
+}
+
 /* O3, Alg. 1 specialised to a symmetric A (the positive-definite matrices the
  * paper targets, Sec. 2.1).  With A12 = A21^T and every inverse symmetric,
  * Alg. 1's III = I A12 equals II^T, so
  *   IV  = A21 III = II A12,
  *   C12 = III VI  = (VI II)^T = C21^T,
  *   VII = III C21 = C12 II,
- * and a node needs four products instead of six.  V-form as in Alg. 1:
- * V = IV - A22, C22 = -VI.  Both triangles of A are read, so the result is
- * the SPD specialisation only for an exactly symmetric A.  The temporaries
- * carry an s suffix (Is = I, IIs = II, ...) to keep them apart from O2's. */
+ * and a node needs four products instead of six.  V and C11 are symmetric
+ * too: only their lower triangles are kept, mirrored onto the upper ones, so
+ * that every block a node passes on (V to the recursion, C11 and C22 to the
+ * parent) is exactly symmetric outside the leaves.  Without that, the
+ * rounding asymmetry of V and C11 breaks III = II^T at the next level and
+ * the residual grows like kappa u.  V-form as in Alg. 1: V = IV - A22,
+ * C22 = -VI.  Both triangles of A are read, so the result is the SPD
+ * specialisation only for an exactly symmetric A.  The temporaries carry an s
+ * suffix (Is = I, IIs = II, ...) to keep them apart from O2's. */
 static int strassen_spd_rec(const double *A, int64_t m, int64_t lda, double *C, int64_t ldc,
                             int64_t leaf, int64_t col0)
 {
@@ -277,6 +290,7 @@ static int strassen_spd_rec(const double *A, int64_t m, int64_t lda, double *C, 
     oracle_gemm(A21, lda, Is, n1, IIs, n2, n2, n1, n1);            /* IIs  = A21 Is     */
     oracle_gemm(IIs, n2, A12, lda, IVs, n2, n2, n2, n1);           /* IVs  = IIs A12    */
     mat_sub(IVs, n2, A22, lda, Vs, n2, n2, n2);                    /* Vs   = IVs - A22  */
+    mat_mirror_lower(Vs, n2, n2);                                  /* Vs symmetric      */
     info = strassen_spd_rec(Vs, n2, n2, VIs, n2, leaf, col0 + n1); /* VIs  = Vs^-1      */
     if (info)
         goto done;
@@ -284,6 +298,7 @@ static int strassen_spd_rec(const double *A, int64_t m, int64_t lda, double *C, 
     mat_transpose(C21, ldc, C12, ldc, n2, n1);                     /* C12  = C21^T      */
     oracle_gemm(C12, ldc, IIs, n2, VIIs, n1, n1, n1, n2);          /* VIIs = C12 IIs    */
     mat_sub(Is, n1, VIIs, n1, C11, ldc, n1, n1);                   /* C11  = Is - VIIs  */
+    mat_mirror_lower(C11, ldc, n1);                                /* C11 symmetric     */
     mat_neg(VIs, n2, C22, ldc, n2, n2);                            /* C22  = -VIs       */
 done:
     free(Is);

@@ -48,6 +48,8 @@ SPD_MUTANTS = {
     "spd_c11_dropped_term": ("mat_sub(Is, n1, VIIs, n1, C11, ldc, n1, n1);",
                              "mat_copy(Is, n1, C11, ldc, n1, n1);"),
     "spd_second_leaf_offset": ("leaf, col0 + n1); /* VIs", "leaf, col0); /* VIs"),
+    "spd_no_v_mirror": ("    mat_mirror_lower(Vs, n2, n2);", "    (void)0;"),
+    "spd_no_c11_mirror": ("    mat_mirror_lower(C11, ldc, n1);", "    (void)0;"),
 }
 
 
@@ -66,6 +68,13 @@ def _spd_pins_pass(lib) -> bool:
     Z[40, :] = 0.0
     _, info = oracle.strassen_inv_spd(Z, 32, lib)
     ok &= info == 41
+    # symmetry outside the leaves, and the residual at kappa = 1e4
+    X, info = oracle.strassen_inv_spd(G, 16, lib)
+    n1 = oracle.split(200)
+    ok &= info == 0 and np.array_equal(X[:n1, :n1], X[:n1, :n1].T)
+    K = W.spd_spectrum(512, 4, kappa=1e4)
+    X, info = oracle.strassen_inv_spd(K, 64, lib)
+    ok &= info == 0 and oracle.residual(K, X) <= 1e-14
     return bool(ok)
 
 

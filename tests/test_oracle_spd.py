@@ -66,16 +66,30 @@ def test_agrees_with_general_recursion(n, leaf):
     assert oracle.forward_error(X3, X2) <= 4 * n * np.linalg.cond(A) * U
 
 
-@pytest.mark.parametrize("n,leaf", [(256, 64), (200, 32), (130, 64)])
-def test_off_diagonal_blocks_are_transposes(n, leaf):
-    """At the top split, C12 = C21^T exactly; the diagonal blocks are only
-    symmetric up to rounding."""
+@pytest.mark.parametrize("n,leaf", [(256, 64), (200, 32), (130, 64), (512, 64)])
+def test_symmetry_outside_the_leaves(n, leaf):
+    """C12 = C21^T exactly; C11 exactly symmetric once it is an internal node
+    (its lower triangle mirrored); only leaf blocks are symmetric merely up
+    to rounding."""
     A = W.spd_gram(n, 6)
     X, info = oracle.strassen_inv_spd(A, leaf)
     assert info == 0
     n1 = oracle.split(n)
     assert np.array_equal(X[:n1, n1:], X[n1:, :n1].T)
+    if n1 > leaf:
+        assert np.array_equal(X[:n1, :n1], X[:n1, :n1].T)
     assert np.linalg.norm(X - X.T) <= 8 * n * U * np.linalg.norm(X)
+
+
+@pytest.mark.parametrize("n,leaf", [(512, 64), (2048, 256)])
+def test_residual_at_kappa_1e4_stays_near_u(n, leaf):
+    """With V and C11 kept symmetric, the residual is that of the general
+    recursion (about 3e-16 at kappa = 1e4); a node that passed an asymmetric
+    V or C11 on would leave it near kappa u (about 2e-13)."""
+    A = W.spd_spectrum(n, 4, kappa=1e4)
+    X, info = oracle.strassen_inv_spd(A, leaf)
+    assert info == 0
+    assert oracle.residual(A, X) <= 1e-14
 
 
 def test_single_leaf_is_gauss_jordan():
