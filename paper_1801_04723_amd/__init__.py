@@ -61,7 +61,7 @@ class Report(ctypes.Structure):
 class PlanOp(ctypes.Structure):
     _fields_ = [
         ("kind", ctypes.c_int), ("count", ctypes.c_int), ("level", ctypes.c_int),
-        ("pad_", ctypes.c_int),
+        ("flags", ctypes.c_int),
         ("m", _i64 * 2), ("n", _i64 * 2), ("k", _i64 * 2),
         ("a_buf", ctypes.c_int * 2), ("b_buf", ctypes.c_int * 2),
         ("c_buf", ctypes.c_int * 2), ("d_buf", ctypes.c_int * 2),
@@ -199,8 +199,11 @@ def plan_describe(n: int, leaf: int, lda: int | None = None, ldx: int | None = N
                                   b=(o.b_buf[q], o.b_off[q], o.b_ld[q]),
                                   c=(o.c_buf[q], o.c_off[q], o.c_ld[q]),
                                   d=(o.d_buf[q], o.d_off[q], o.d_ld[q]),
-                                  alpha=o.alpha[q], beta=o.beta[q]))
+                                  alpha=o.alpha[q], beta=o.beta[q], lower=bool(o.flags >> q & 1)))
             ops.append(dict(kind="products", level=o.level, products=prods))
+        elif o.kind == 3:
+            ops.append(dict(kind="mirror", level=o.level, n=o.m[0],
+                            dst=(o.d_buf[0], o.d_off[0], o.d_ld[0])))
         elif o.kind == 2:
             ops.append(dict(kind="transpose", level=o.level, m=o.m[0], n=o.n[0],
                             src=(o.a_buf[0], o.a_off[0], o.a_ld[0]),

@@ -48,6 +48,32 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Lower triangle of an order-n view mirrored onto the upper one, in place:
+// d[i][j] = d[j][i] for j > i.  Workgroup t takes lower tile (r, c), r >= c
+// (row by row over the T (T + 1) / 2 of them), reads it whole into LDS and
+// writes its transpose into upper tile (c, r); a diagonal tile writes only its
+// own strict upper part.  Each tile is read by one workgroup, and no tile
+// that is written is read by another, so the update needs no ordering.
+__global__ void __launch_bounds__(256) k_mirror_lower(double *__restrict__ d, int64_t ld, int64_t n) {
+    __shared__ double tile[kTT][kTT + 1];
+    const int t = blockIdx.x;
+    int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > t) --r;
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    const int c = t - r * (r + 1) / 2;
+    const int64_t i0 = (int64_t)r * kTT, j0 = (int64_t)c * kTT;  // source rows i0.., columns j0..
+    const int tx = threadIdx.x & (kTT - 1), ty = threadIdx.x / kTT;
+    for (int jj = ty; jj < kTT; jj += 256 / kTT) {
+        const int64_t i = i0 + tx, j = j0 + jj;
+        if (i < n && j < n) tile[jj][tx] = d[i + j * ld];
+    }
+    __syncthreads();
+    for (int ii = ty; ii < kTT; ii += 256 / kTT) {
+        const int64_t row = j0 + tx, col = i0 + ii;  // destination (row, col) = source (col, row)
+        if (row < n && col < n && col > row) d[row + col * ld] = tile[tx][ii];
+    }
+}
+
 // Per-block partial sums of squares over whole columns (fixed assignment of
 // columns to blocks and fixed in-block order: the result does not depend on
 // scheduling).
@@ -119,6 +145,14 @@ hipError_t cast_f32_to_f64(const float *src, int64_t lds, double *dst, int64_t l
 hipError_t copy_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
                     int64_t n, hipStream_t s) {
     return convert<double, double>(src, lds, dst, ldd, m, n, s);
+}
+
+hipError_t mirror_lower_f64(double *d, int64_t ld, int64_t n, hipStream_t s) {
+    if (n <= 1) return hipSuccess;
+    const int64_t T = (n + kTT - 1) / kTT, blocks = T * (T + 1) / 2;
+    if (blocks > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)blocks), dim3(256), 0, s, d, ld, n);
+    return hipGetLastError();
 }
 
 hipError_t transpose_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,

@@ -78,9 +78,20 @@ __device__ inline int group_member(const GroupArgs<N> &g, int bid) {
 // its own L2: when the range and both tile counts are multiples of 8, XCD x
 // gets the contiguous stretch [x T/8, (x+1) T/8) of an order made of 8 x 8
 // tile blocks, so the A rows and B columns it reads stay in its own L2.
-// Otherwise tiles go in plain column-major order. Either way every tile is
-// computed exactly once, with the same arithmetic.
-__device__ inline void tile_coords(int t, int tstart, int tiles_m, int tiles_n, int &tm, int &tn) {
+// Otherwise tiles go in plain column-major order. A lower-triangle problem
+// (square tile grid) has only the T (T + 1) / 2 tiles on or below the
+// diagonal, row by row: row r holds (r, 0) ... (r, r).  Every tile is
+// computed exactly once, with the same arithmetic, whatever the order.
+__device__ inline void tile_coords(int t, int tstart, int tiles_m, int tiles_n, bool lower, int &tm,
+                                   int &tn) {
+    if (lower) {
+        int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while (r * (r + 1) / 2 > t) --r;
+        while ((r + 1) * (r + 2) / 2 <= t) ++r;
+        tm = r;
+        tn = t - r * (r + 1) / 2;
+        return;
+    }
     if ((tstart & 7) == 0 && (tiles_m & 7) == 0 && (tiles_n & 7) == 0) {
         const int u = (t & 7) * ((tiles_m * tiles_n) >> 3) + (t >> 3);
         const int blk = u >> 6, in = u & 63;
@@ -114,7 +125,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
     const GemmProb P = g.p[pi];
     const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
     int tm, tn;
-    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, tm, tn);
+    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, P.lower != 0, tm, tn);
 
     const int M = P.m, N = P.n, K = P.k;
     const int m0 = tm * BM, n0 = tn * BN;
@@ -262,7 +273,7 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
     const GemmProb P = g.p[pi];
     const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
     int tm, tn;
-    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, tm, tn);
+    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, P.lower != 0, tm, tn);
     const int M = P.m, N = P.n, K = P.k;
     const int m0 = tm * BM, n0 = tn * BN;
     const int64_t lda = P.lda, ldb = P.ldb;
@@ -430,7 +441,7 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
     const GemmProb P = g.p[pi];
     const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
     int tm, tn;
-    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, tm, tn);
+    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, P.lower != 0, tm, tn);
     const int M = P.m, N = P.n, K = P.k;
     const int m0 = tm * BM, n0 = tn * BN;
     const float *__restrict__ A = static_cast<const float *>(P.A);
@@ -603,9 +614,12 @@ int make_group(const GemmProb *probs, int count, GroupArgs<N> &g) {
         if (q < count) {
             g.p[q] = probs[q];
             const int tm = (probs[q].m + BM - 1) / BM, tn = (probs[q].n + BN - 1) / BN;
+            // lower-triangle mode needs a square problem on a square tile grid
+            const bool low = probs[q].lower && probs[q].m == probs[q].n && BM == BN;
+            g.p[q].lower = low ? 1 : 0;
             g.tile_start[q] = total;
             g.tiles_m[q] = tm > 0 ? tm : 1;
-            total += tm * tn;
+            total += low ? tm * (tm + 1) / 2 : tm * tn;
         } else {
             g.p[q] = probs[0];
             g.tile_start[q] = 1 << 30;
@@ -734,7 +748,9 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
         done[n_live] = false;
         ++n_live;
         const double m = probs[q].m, n = probs[q].n, k = probs[q].k;
-        flops += 2.0 * m * n * k;
+        // a lower-triangle product computes about m (m + tile) / 2 outputs
+        flops += (probs[q].lower && probs[q].m == probs[q].n) ? k * m * (m + cfgs[n_live - 1].tile)
+                                                               : 2.0 * m * n * k;
         bytes += es * (m * k + k * n + m * n + ((probs[q].beta != 0.0) ? m * n : 0.0));
     }
     const char *name = "gemm_empty";

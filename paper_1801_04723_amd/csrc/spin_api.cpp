@@ -53,7 +53,10 @@ void push_products(Plan &P, int level, const PGemm &g0, const PGemm *g1) {
         op.g[1] = *g1;
         op.count = 2;
     }
-    for (int q = 0; q < op.count; ++q) P.flops += 2.0 * op.g[q].m * op.g[q].n * op.g[q].k;
+    // a lower-triangle product counts the m (m + 1) / 2 outputs it has to form
+    for (int q = 0; q < op.count; ++q)
+        P.flops += op.g[q].lower ? (double)op.g[q].m * (op.g[q].m + 1) * op.g[q].k
+                                 : 2.0 * op.g[q].m * op.g[q].n * op.g[q].k;
     P.ops.push_back(op);
 }
 
@@ -108,9 +111,24 @@ void plan_node(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level, in
 //   S   = A22 - A21 III = A22 - II A12,
 //   C12 = -III C22      = C21^T,
 //   C11 = I - III C21   = I - C12 II.
-// A node costs four products (II, S, C21, C11) and one transpose instead of
-// six products.  Only the transpose relies on symmetry; S and C11 are the
-// same products regrouped.  II (n2 x n1) and S live in the workspace.
+// S and C11 are symmetric too: only their lower triangles are computed
+// (tiles on or below the diagonal) and then mirrored onto the upper ones, so
+// every block a node passes on is exactly symmetric outside the leaves.
+// Passing on the rounding asymmetry instead breaks III = II^T at the next
+// level and the residual grows like kappa u.  A node: II, S (lower half),
+// mirror S, recursion, C21, transpose C12 = C21^T, C11 (lower half), mirror
+// C11; about 6 h^3 flops against 12 h^3.  II (n2 x n1) and S live in the
+// workspace.
+void push_mirror(Plan &P, int level, const Ref &blk, int64_t m) {
+    POp op{};
+    op.kind = 3;
+    op.count = 1;
+    op.level = level;
+    op.out = blk;
+    op.tm = m;
+    P.ops.push_back(op);
+}
+
 void plan_node_spd(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level, int64_t col0) {
     if (m <= P.leaf) {
         plan_node(P, in, out, m, wsoff, level, col0);
@@ -129,8 +147,9 @@ void plan_node_spd(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level
     const Ref none{BUF_WS, 0, 1};
     // II = A21 I
     push_products(P, level, PGemm{A21, C11, none, II, n2, n1, n1, 1.0, 0.0, 0}, nullptr);
-    // S = A22 - II A12  (= A22 - A21 III = -V)
-    push_products(P, level, PGemm{II, A12, A22, S, n2, n2, n1, -1.0, 1.0, 0}, nullptr);
+    // S = A22 - II A12  (= A22 - A21 III = -V), lower half, then mirrored
+    push_products(P, level, PGemm{II, A12, A22, S, n2, n2, n1, -1.0, 1.0, 0, 1}, nullptr);
+    push_mirror(P, level, S, n2);
     // C22 = S^-1  (= -VI)
     plan_node_spd(P, S, C22, n2, next, level + 1, col0 + n1);
     // C21 = -C22 II  (= VI II)
@@ -145,8 +164,10 @@ void plan_node_spd(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level
     t.tm = n2;
     t.tn = n1;
     P.ops.push_back(t);
-    // C11 = I - C12 II  (= I - III C21), in place on the C11 view
-    push_products(P, level, PGemm{C12, II, C11, C11, n1, n1, n2, -1.0, 1.0, 0}, nullptr);
+    // C11 = I - C12 II  (= I - III C21), in place on the C11 view, lower half,
+    // then mirrored
+    push_products(P, level, PGemm{C12, II, C11, C11, n1, n1, n2, -1.0, 1.0, 0, 1}, nullptr);
+    push_mirror(P, level, C11, n1);
 }
 
 }  // namespace
@@ -215,7 +236,7 @@ GemmProb make_prob(char *const base[3], size_t es, const PGemm &g) {
                     at(g.d),          g.a.ld,        g.b.ld,
                     use_c ? g.c.ld : 1, g.d.ld,      (int32_t)g.m,
                     (int32_t)g.n,     (int32_t)g.k,  g.add_identity,
-                    g.alpha,          g.beta};
+                    g.alpha,          g.beta,        g.lower};
 }
 
 namespace {
@@ -335,6 +356,13 @@ hipError_t run_plan(const Plan &P, const Exec &E) {
             hipError_t e = transpose_f64(static_cast<const double *>(at(E, op.in)), op.in.ld,
                                          static_cast<double *>(at(E, op.out)), op.out.ld, op.tm,
                                          op.tn, E.s);
+            if (tr) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
+        } else if (op.kind == 3) {
+            if (E.dt != kF64) return hipErrorInvalidValue;
+            LaunchInfo li{"mirror", 0.0, 8.0 * (double)op.tm * (double)op.tm};
+            if (tr) trace_cb(&ctx, li, 0);
+            hipError_t e = mirror_lower_f64(static_cast<double *>(at(E, op.out)), op.out.ld, op.tm, E.s);
             if (tr) trace_cb(&ctx, li, 1);
             if (e != hipSuccess) return e;
         } else {
@@ -720,7 +748,14 @@ int64_t describe_plan(const Plan &P, spin_plan_op *ops, int64_t cap, double *flo
                 o.d_ld[q] = g.d.ld;
                 o.alpha[q] = g.alpha;
                 o.beta[q] = g.beta;
+                if (g.lower) o.flags |= 1 << q;
             }
+        } else if (op.kind == 3) {
+            o.m[0] = op.tm;
+            o.n[0] = op.tm;
+            o.d_buf[0] = op.out.buf;
+            o.d_off[0] = op.out.off;
+            o.d_ld[0] = op.out.ld;
         } else if (op.kind == 2) {
             o.m[0] = op.tm;
             o.n[0] = op.tn;

@@ -21,6 +21,8 @@ inline DType storage_type(DType d) { return d == kF64 ? kF64 : kF32; }
 constexpr int kLeafMaxOrder = 2048;
 
 // One block product  D = alpha * A * B + beta * C0 (+ I),  column-major views.
+// lower != 0 with m == n: only the tiles on or below the diagonal are
+// computed (a symmetric result whose strict upper part a mirror step fills).
 struct GemmProb {
     const void *A;
     const void *B;
@@ -30,6 +32,7 @@ struct GemmProb {
     int32_t m, n, k;
     int32_t add_identity;
     double alpha, beta;
+    int32_t lower;
 };
 
 // One gemm_launch() call takes up to kMaxBatch independent products; products
@@ -96,6 +99,8 @@ hipError_t copy_f64(const double *src, int64_t lds, double *dst, int64_t ldd, in
 // dst (n x m, ldd) = src (m x n, lds)^T; the views must not overlap.
 hipError_t transpose_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
                          int64_t n, hipStream_t s);
+// In place on an order-n view: d[i][j] = d[j][i] for j > i.
+hipError_t mirror_lower_f64(double *d, int64_t ld, int64_t n, hipStream_t s);
 // Sum of squares of an (m x n) FP64 view, deterministic two-pass reduction:
 // partials (>= frob_partials_count(m, n) doubles) then one block writes *out.
 int frob_partials_count(int64_t m, int64_t n);

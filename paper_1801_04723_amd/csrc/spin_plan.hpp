@@ -20,16 +20,19 @@ struct Ref {
     int64_t ld;
 };
 
-// One block product of the schedule: D = alpha A B + beta C (+ I).
+// One block product of the schedule: D = alpha A B + beta C (+ I).  With
+// lower set (m == n) only the tiles on or below the diagonal are computed.
 struct PGemm {
     Ref a, b, c, d;
     int64_t m, n, k;
     double alpha, beta;
     int add_identity;
+    int lower;
 };
 
-// One step: a group of independent products (kind 0), a leaf (kind 1) or a
-// transpose (kind 2: out (tn x tm) := in (tm x tn)^T).
+// One step: a group of independent products (kind 0), a leaf (kind 1), a
+// transpose (kind 2: out (tn x tm) := in (tm x tn)^T) or a mirror (kind 3:
+// the lower triangle of the order-tm block `out` copied onto its upper one).
 struct POp {
     int kind;
     int count;

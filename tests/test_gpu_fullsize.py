@@ -87,13 +87,14 @@ def test_mixed_spd_16384(torch_cuda, mode, steps):
 
 def test_spd_variant_16384_kappa_1e4(torch_cuda):
     """spin_invert_spd on the mixed-precision matrix (kappa = 1e4), leaf 256:
-    its residual grows like kappa u but stays within 1e-12."""
+    with S and C11 kept symmetric its residual stays at the general path's
+    level (an asymmetric variant reaches about 2e-13 here)."""
     import paper_1801_04723_amd as S
     torch = torch_cuda
     A = W.torch_spd_spectrum(N, seed=4, kappa=1e4)
     X = S.invert_spd(A, leaf=256)
     assert S.info() == 0
-    assert S.residual(A, X) <= 1e-12
+    assert S.residual(A, X) <= 1e-14
     cols = _sampled_columns(torch, N, 6, 9)
     assert _column_residual(torch, A, X, cols) <= 1e-12
     del A, X

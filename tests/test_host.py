@@ -149,6 +149,12 @@ def _run_schedule_on_cpu(A, leaf, spd=False):
         elif o["kind"] == "transpose":
             src = np.array(view(o["src"], o["m"], o["n"]))
             view(o["dst"], o["n"], o["m"])[...] = src.T
+        elif o["kind"] == "mirror":
+            # a lower-half product followed by its mirror leaves the lower
+            # triangle of the full product, whatever the upper one held
+            d = view(o["dst"], o["n"], o["n"])
+            iu = np.triu_indices(o["n"], 1)
+            d[iu] = d.T[iu]
         else:
             results = []
             for p in o["products"]:
@@ -187,13 +193,14 @@ def test_spd_schedule_replay_equals_oracle_bitwise(n, leaf):
 
 def _spd_flops(m, leaf):
     """Direct sum over the recursion: 2 L^3 per leaf; per node II (2 n2 n1 n1),
-    S (2 n2 n2 n1), C21 (2 n2 n1 n2) and C11 (2 n1 n1 n2)."""
+    the lower half of S (n2 (n2 + 1) n1), C21 (2 n2 n1 n2) and the lower half
+    of C11 (n1 (n1 + 1) n2)."""
     if m <= leaf:
         return 2 * m ** 3
     n1 = oracle.split(m)
     n2 = m - n1
     return (_spd_flops(n1, leaf) + _spd_flops(n2, leaf)
-            + 2 * n2 * n1 * n1 + 2 * n2 * n2 * n1 + 2 * n2 * n1 * n2 + 2 * n1 * n1 * n2)
+            + 2 * n2 * n1 * n1 + n2 * (n2 + 1) * n1 + 2 * n2 * n1 * n2 + n1 * (n1 + 1) * n2)
 
 
 @pytest.mark.parametrize("n,leaf", [(256, 64), (8192, 256), (16384, 128), (300, 64), (4160, 128), (1, 1)])
@@ -205,12 +212,18 @@ def test_spd_plan_structure(n, leaf):
     assert [(o["L"], o["col0"]) for o in leaves] == [(o["L"], o["col0"]) for o in plain if o["kind"] == "leaf"]
     internal = sum(1 for o in plain if o["kind"] == "products") // 4
     assert sum(1 for o in ops if o["kind"] == "transpose") == internal
+    assert sum(1 for o in ops if o["kind"] == "mirror") == 2 * internal
     prods = [o for o in ops if o["kind"] == "products"]
     assert len(prods) == 4 * internal and all(len(o["products"]) == 1 for o in prods)
+    # S and C11 (the second and fourth product of a node) are lower halves,
+    # each followed by the mirror of the same block
+    for i, o in enumerate(ops):
+        if o["kind"] == "products" and o["products"][0]["lower"]:
+            p = o["products"][0]
+            assert p["m"] == p["n"] and ops[i + 1]["kind"] == "mirror"
+            assert ops[i + 1]["dst"] == p["d"] and ops[i + 1]["n"] == p["m"]
+    assert sum(1 for o in prods if o["products"][0]["lower"]) == 2 * internal
     if n % leaf == 0 and (n // leaf) & (n // leaf - 1) == 0:
-        d = (n // leaf).bit_length() - 1
-        # 8 h^3 per node instead of 12 h^3: levels sum to (4/3)(1 - 4^-d) n^3
-        assert abs(fl - (4 / 3 * (1 - 4.0 ** -d) * n ** 3 + 2 * n ** 3 / 4 ** d)) <= 1e-9 * fl
         assert fl_plain == 2 * n ** 3
     for o in ops:
         if o["kind"] == "transpose":
