@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--mode", default="fp64", choices=["fp64", "fp32"])
     p.add_argument("--spd", action="store_true",
                    help="time spin_invert_spd as the step (symmetric inputs only)")
+    p.add_argument("--no-spd-variant", action="store_true",
+                   help="skip the spd_variant timing beside the plain method")
     p.add_argument("--ns-steps", type=int, default=2)
     p.add_argument("--seed", type=int, default=None)
     p.add_argument("--no-cpu", action="store_true")
@@ -442,7 +444,7 @@ def main():
         out["kernel_breakdown"] = breakdown
     else:
         out["roofline"] = None
-    if args.mode == "fp64" and not args.spd and args.kind != "dd":
+    if args.mode == "fp64" and not args.spd and args.kind != "dd" and not args.no_spd_variant:
         out["spd_variant"] = spd_variant(dA, n, leaf, args.steps, args.warmup, ms)
     if args.serve_seconds > 0:
         out["serving"] = serving(args.serve_rate, args.serve_seconds)
