@@ -669,8 +669,15 @@ struct Cfg {
 Cfg choose_cfg(const GemmProb &p, DType dt) {
     const int es = dt == kF64 ? 8 : 4;
     const int vw = 16 / es;
-    const int64_t t128 = (int64_t)((p.m + 127) / 128) * ((p.n + 127) / 128);
-    const int64_t t64 = (int64_t)((p.m + 63) / 64) * ((p.n + 63) / 64);
+    // a lower-triangle problem runs only the T (T + 1) / 2 tiles on or below
+    // the diagonal, so that is the count that has to fill the GPU
+    const bool low = p.lower && p.m == p.n;
+    auto count = [&](int64_t t) {
+        const int64_t tm = (p.m + t - 1) / t, tn = (p.n + t - 1) / t;
+        return low ? tm * (tm + 1) / 2 : tm * tn;
+    };
+    const int64_t t128 = count(128);
+    const int64_t t64 = count(64);
     Cfg c;
     c.tile = (t128 >= 192) ? 128 : (t64 >= 128) ? 64 : 32;
     const bool aligned =
