@@ -62,6 +62,18 @@ def test_argument_validation_codes():
     assert L.spin_invert_mixed(A, 8, 8, X, 8, 2, 0, 2, None, s) == -6  # FP64 is not mixed
     assert L.spin_invert_mixed(A, 8, 8, X, 8, 2, 4, 2, None, s) == -6
     assert L.spin_gemm(4, 4, 4, 4, 1.0, A, 4, A, 4, 0.0, None, 4, X, 4, 0, s) == -6
+    # the symmetric variant validates exactly like spin_invert, before any GPU work
+    assert L.spin_invert_spd(None, 4, 4, X, 4, 2, s) == -1
+    assert L.spin_invert_spd(A, 0, 4, X, 4, 2, s) == -2
+    assert L.spin_invert_spd(A, 8, 4, X, 8, 2, s) == -3
+    assert L.spin_invert_spd(A, 8, 8, X, 7, 2, s) == -3
+    assert L.spin_invert_spd(A, 8, 8, X, 8, 0, s) == -4
+    assert L.spin_invert_spd(A, 8, 8, X, 8, 4096, s) == -4
+    assert L.spin_invert_spd(A, 8, 8, p(0x10000000 + 8 * 60), 8, 2, s) == -5
+    assert L.spin_plan_describe_spd(0, 1, 1, 1, None, 0, None) == -2
+    assert L.spin_plan_describe_spd(8, 4, 8, 2, None, 0, None) == -3
+    assert L.spin_plan_describe_spd(8, 8, 8, 0, None, 0, None) == -4
+    assert L.spin_plan_describe_spd(8, 8, 8, 2, None, 3, None) == -1
 
 
 def test_mixed_modes_share_one_layout():
