@@ -28,9 +28,9 @@
  *              stream) and returns before the GPU finishes.  Calls on one
  *              stream are ordered; calls from several host threads must use
  *              different streams.
- *   Graphs     the first inversion with a given mode, order, leading
- *              dimensions, buffers and stream workspace records its launch
- *              sequence as a HIP graph; later identical calls replay it.  At
+ *   Graphs     the first inversion with a given entry point, mode, order,
+ *              leading dimensions, buffers and stream workspace records its
+ *              launch sequence as a HIP graph; later identical calls replay it.  At
  *              most 64 graphs are kept (the cache is emptied when full, after
  *              waiting for the device).  The environment variable
  *              SPIN_NO_GRAPH=1 makes every call launch its kernels directly.
