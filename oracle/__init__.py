@@ -14,6 +14,9 @@ Contents
                          positive-definite matrices of Sec. 2.1): III = II^T,
                          so IV = II A12, C12 = C21^T and VII = C12 II; V and
                          C11 keep their lower triangles, mirrored.
+  * ``lu_inv``        -- O4, inversion through a block LU factorisation
+                         without pivoting: L^-1 and U^-1 by block recursion,
+                         then X = U^-1 L^-1 (the paper's comparison method).
   * ``gemm``          -- the plain matrix product of ``multiply`` (Sec. 3.3).
   * ``ns_step``       -- one Newton refinement step X + X (I - A X)
                          (Newton iteration as Strassen-inversion stabiliser,
@@ -64,6 +67,8 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_strassen_inv.restype = ctypes.c_int
     lib.oracle_strassen_inv_spd.argtypes = [dp, i64, i64, dp, i64, i64]
     lib.oracle_strassen_inv_spd.restype = ctypes.c_int
+    lib.oracle_lu_inv.argtypes = [dp, i64, i64, dp, i64, i64]
+    lib.oracle_lu_inv.restype = ctypes.c_int
     lib.oracle_ns_step.argtypes = [dp, i64, i64, dp, i64, dp, i64]
     lib.oracle_ns_step.restype = ctypes.c_int
     lib.oracle_split.argtypes = [i64]
@@ -135,6 +140,17 @@ def strassen_inv_spd(a, leaf: int, lib: ctypes.CDLL | None = None):
     assert a.shape == (n, n)
     x = np.zeros((n, n), dtype=np.float64, order="F")
     info = lib.oracle_strassen_inv_spd(_ptr(a), n, max(n, 1), _ptr(x), max(n, 1), int(leaf))
+    return x, int(info)
+
+
+def lu_inv(a, leaf: int, lib: ctypes.CDLL | None = None):
+    """O4 (block LU without pivoting, X = U^-1 L^-1): returns (X, info)."""
+    lib = lib or load()
+    a = _f64(a)
+    n = a.shape[0]
+    assert a.shape == (n, n)
+    x = np.zeros((n, n), dtype=np.float64, order="F")
+    info = lib.oracle_lu_inv(_ptr(a), n, max(n, 1), _ptr(x), max(n, 1), int(leaf))
     return x, int(info)
 
 

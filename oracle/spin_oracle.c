@@ -320,6 +320,132 @@ int oracle_strassen_inv_spd(const double *A, int64_t n, int64_t lda, double *X, 
     return strassen_spd_rec(A, n, lda, X, ldx, leaf, 0);
 }
 
+/* Leaf of O4: A = L U without pivoting (Doolittle: unit lower L), then
+ * Li = L^-1 by forward substitution and Ui = U^-1 by back substitution, each
+ * written as a full m x m block (zeros in the other triangle).  Returns 0, or
+ * the 1-based column of the first zero or non-finite pivot. */
+static int lu_leaf(const double *A, int64_t m, int64_t lda, double *Li, int64_t ldl, double *Ui,
+                   int64_t ldu)
+{
+    double *F = dalloc(m, m);
+    if (!F)
+        return -1;
+    mat_copy(A, lda, F, m, m, m);
+    int info = 0;
+    for (int64_t k = 0; k < m && !info; ++k) {
+        const double piv = AT(F, k, k, m);
+        if (piv == 0.0 || !isfinite(piv)) {
+            info = (int)(k + 1);
+            break;
+        }
+        for (int64_t i = k + 1; i < m; ++i)
+            AT(F, i, k, m) = AT(F, i, k, m) / piv;                 /* multiplier l_ik */
+        for (int64_t j = k + 1; j < m; ++j)
+            for (int64_t i = k + 1; i < m; ++i)
+                AT(F, i, j, m) = AT(F, i, j, m) - AT(F, i, k, m) * AT(F, k, j, m);
+    }
+    for (int64_t j = 0; j < m && !info; ++j) {
+        /* column j of L^-1: x_j = 1, x_i = -sum_{j<=k<i} l_ik x_k for i > j */
+        for (int64_t i = 0; i < m; ++i) {
+            double x = 0.0;
+            if (i == j) {
+                x = 1.0;
+            } else if (i > j) {
+                for (int64_t k = j; k < i; ++k)
+                    x = x - AT(F, i, k, m) * AT(Li, k, j, ldl);
+            }
+            AT(Li, i, j, ldl) = x;
+        }
+        /* column j of U^-1: x_j = 1/u_jj, x_i = -(sum_{i<k<=j} u_ik x_k)/u_ii for i < j */
+        for (int64_t i = m - 1; i >= 0; --i) {
+            double x = 0.0;
+            if (i == j) {
+                x = 1.0 / AT(F, j, j, m);
+            } else if (i < j) {
+                for (int64_t k = i + 1; k <= j; ++k)
+                    x = x - AT(F, i, k, m) * AT(Ui, k, j, ldu);
+                x = x / AT(F, i, i, m);
+            }
+            AT(Ui, i, j, ldu) = x;
+        }
+    }
+    free(F);
+    return info;
+}
+
+/* Block recursion of O4: Li = L^-1 and Ui = U^-1 of the factors of A = L U
+ * (no pivoting across or inside blocks), Li and Ui written as full blocks.
+ *   (Li11, Ui11) = rec(A11);  U12 = Li11 A12;  L21 = A21 Ui11;
+ *   S = A22 - L21 U12;  (Li22, Ui22) = rec(S);
+ *   Li21 = -Li22 (L21 Li11);  Ui12 = -(Ui11 U12) Ui22;
+ *   Li12 = 0;  Ui21 = 0. */
+static int lu_rec(const double *A, int64_t m, int64_t lda, double *Li, int64_t ldl, double *Ui,
+                  int64_t ldu, int64_t leaf, int64_t col0)
+{
+    if (m <= leaf) {
+        int info = lu_leaf(A, m, lda, Li, ldl, Ui, ldu);
+        return info > 0 ? (int)(info + col0) : info;
+    }
+    const int64_t n1 = oracle_split(m), n2 = m - n1;
+    const double *A12 = &AT(A, 0, n1, lda), *A21 = &AT(A, n1, 0, lda), *A22 = &AT(A, n1, n1, lda);
+    double *U12 = dalloc(n1, n2), *L21 = dalloc(n2, n1), *P = dalloc(n2, n2);
+    double *S = dalloc(n2, n2), *T1 = dalloc(n2, n1), *T2 = dalloc(n1, n2);
+    int info = -1;
+    if (!U12 || !L21 || !P || !S || !T1 || !T2)
+        goto done;
+    info = lu_rec(A, n1, lda, Li, ldl, Ui, ldu, leaf, col0);
+    if (info)
+        goto done;
+    oracle_gemm(Li, ldl, A12, lda, U12, n1, n1, n2, n1);                /* U12 = Li11 A12  */
+    oracle_gemm(A21, lda, Ui, ldu, L21, n2, n2, n1, n1);                /* L21 = A21 Ui11  */
+    oracle_gemm(L21, n2, U12, n1, P, n2, n2, n2, n1);                   /* P = L21 U12     */
+    mat_sub(A22, lda, P, n2, S, n2, n2, n2);                            /* S = A22 - P     */
+    info = lu_rec(S, n2, n2, &AT(Li, n1, n1, ldl), ldl, &AT(Ui, n1, n1, ldu), ldu, leaf, col0 + n1);
+    if (info)
+        goto done;
+    oracle_gemm(L21, n2, Li, ldl, T1, n2, n2, n1, n1);                  /* T1 = L21 Li11   */
+    oracle_gemm(Ui, ldu, U12, n1, T2, n1, n1, n2, n1);                  /* T2 = Ui11 U12   */
+    oracle_gemm(&AT(Li, n1, n1, ldl), ldl, T1, n2, &AT(Li, n1, 0, ldl), ldl, n2, n1, n2);
+    mat_neg(&AT(Li, n1, 0, ldl), ldl, &AT(Li, n1, 0, ldl), ldl, n2, n1); /* Li21 = -Li22 T1 */
+    oracle_gemm(T2, n1, &AT(Ui, n1, n1, ldu), ldu, &AT(Ui, 0, n1, ldu), ldu, n1, n2, n2);
+    mat_neg(&AT(Ui, 0, n1, ldu), ldu, &AT(Ui, 0, n1, ldu), ldu, n1, n2); /* Ui12 = -T2 Ui22 */
+    for (int64_t j = n1; j < m; ++j)
+        for (int64_t i = 0; i < n1; ++i)
+            AT(Li, i, j, ldl) = 0.0;                                    /* Li12 = 0        */
+    for (int64_t j = 0; j < n1; ++j)
+        for (int64_t i = n1; i < m; ++i)
+            AT(Ui, i, j, ldu) = 0.0;                                    /* Ui21 = 0        */
+done:
+    free(U12);
+    free(L21);
+    free(P);
+    free(S);
+    free(T1);
+    free(T2);
+    return info;
+}
+
+/* O4: inversion through a block LU factorisation, the method the paper
+ * compares against (Sec. 5, after Liu et al.): A = L U without pivoting,
+ * L^-1 and U^-1 by block recursion, then X = U^-1 L^-1. */
+int oracle_lu_inv(const double *A, int64_t n, int64_t lda, double *X, int64_t ldx, int64_t leaf)
+{
+    if (n <= 0)
+        return 0;
+    if (leaf < 1)
+        return -2;
+    double *Li = dalloc(n, n), *Ui = dalloc(n, n);
+    int info = -1;
+    if (Li && Ui) {
+        info = lu_rec(A, n, lda, Li, n, Ui, n, leaf, 0);
+        if (!info)
+            oracle_gemm(Ui, n, Li, n, X, ldx, n, n, n);                  /* X = Ui Li       */
+    }
+    free(Li);
+    free(Ui);
+    return info;
+}
+
 /* One refinement step: Xn = X + X (I - A X). */
 int oracle_ns_step(const double *A, int64_t n, int64_t lda, const double *X, int64_t ldx,
                    double *Xn, int64_t ldxn)

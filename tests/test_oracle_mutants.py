@@ -53,6 +53,40 @@ SPD_MUTANTS = {
 }
 
 
+# Mistakes planted in O4, the block-LU inversion.
+LU_MUTANTS = {
+    "lu_multiplier_not_divided": ("AT(F, i, k, m) = AT(F, i, k, m) / piv;                 /* multiplier l_ik */",
+                                  "AT(F, i, k, m) = AT(F, i, k, m);"),
+    "lu_li21_sign": ("mat_neg(&AT(Li, n1, 0, ldl), ldl, &AT(Li, n1, 0, ldl), ldl, n2, n1); /* Li21 = -Li22 T1 */",
+                     "(void)0;"),
+    "lu_u12_operand_order": ("oracle_gemm(Li, ldl, A12, lda, U12, n1, n1, n2, n1);                /* U12 = Li11 A12  */",
+                             "oracle_gemm(A12, lda, Li, ldl, U12, n1, n1, n2, n1);"),
+    "lu_no_zero_fill": ("            AT(Li, i, j, ldl) = 0.0;                                    /* Li12 = 0        */",
+                        "            (void)0;"),
+    "lu_final_order": ("oracle_gemm(Ui, n, Li, n, X, ldx, n, n, n);                  /* X = Ui Li       */",
+                       "oracle_gemm(Li, n, Ui, n, X, ldx, n, n, n);"),
+    "lu_second_leaf_offset": ("ldu, leaf, col0 + n1);", "ldu, leaf, col0);"),
+}
+
+
+def _lu_pins_pass(lib) -> bool:
+    """A compact set of the pins from test_oracle_lu; True iff all hold."""
+    ok = True
+    A = W.unimodular_bidiag(32, seed=40)
+    X, info = oracle.lu_inv(A, 8, lib)
+    ok &= info == 0 and np.array_equal(X, to_float(exact_inverse(A)))
+    G = W.diag_dominant(200, 2)
+    X, info = oracle.lu_inv(G, 32, lib)
+    ref = np.linalg.inv(G)
+    ok &= info == 0 and np.linalg.norm(X - ref) / np.linalg.norm(ref) < 1e-12
+    Z = W.diag_dominant(64, seed=8)
+    Z[:, 40] = 0.0
+    Z[40, :] = 0.0
+    _, info = oracle.lu_inv(Z, 32, lib)
+    ok &= info == 41
+    return bool(ok)
+
+
 def _spd_pins_pass(lib) -> bool:
     """A compact set of the pins from test_oracle_spd; True iff all hold."""
     ok = True
@@ -128,6 +162,7 @@ def test_unmutated_passes(tmp_path):
     lib = oracle.load(out)
     assert _pins_pass(lib)
     assert _spd_pins_pass(lib)
+    assert _lu_pins_pass(lib)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -142,3 +177,10 @@ def test_spd_mutant_is_caught(tmp_path, name):
     old, new = SPD_MUTANTS[name]
     lib = _build_variant(tmp_path, name, old, new)
     assert not _spd_pins_pass(lib), f"mutant {name} survived the O3 pins"
+
+
+@pytest.mark.parametrize("name", sorted(LU_MUTANTS))
+def test_lu_mutant_is_caught(tmp_path, name):
+    old, new = LU_MUTANTS[name]
+    lib = _build_variant(tmp_path, name, old, new)
+    assert not _lu_pins_pass(lib), f"mutant {name} survived the O4 pins"
