@@ -67,6 +67,9 @@ def parse():
     p.add_argument("--mixed-reps", type=int, default=2)
     p.add_argument("--gemm-sweep", action="store_true",
                    help="only time spin_gemm alone (FP64, FP32, BF16, bf16x3; h = 2048, 4096, 8192) and exit")
+    p.add_argument("--lu-compare", action="store_true",
+                   help="only time Alg. 1 against inversion through a block LU factorisation "
+                        "(U(-1,1) + n I, n = 8192 and 16384, leaf 128) and exit")
     p.add_argument("--cost-model", action="store_true",
                    help="only calibrate the recursion cost model, predict the leaf sweep at n = 16384 "
                         "(and n = 8192, leaf 256), time the same inversions and exit")
@@ -266,6 +269,34 @@ def roofline_from_trace(recs, n_steps: int):
     }, breakdown
 
 
+def lu_compare_run():
+    """Alg. 1 (spin_invert) against inversion through a block LU factorisation
+    (spin_invert_lu) on the same matrices, the paper's SPIN-vs-LU comparison on
+    one GPU: time per inversion (HIP events, 1 warm-up + 3), residual, and the
+    schedule flops of each."""
+    import torch
+    import paper_1801_04723_amd as spin
+    from paper_1801_04723_amd import costmodel as C
+    import workloads as W
+    rows = []
+    for n, leaf in [(8192, 128), (16384, 128)]:
+        A = W.torch_diag_dominant(n, seed=3)
+        X = torch.empty_like(A)
+        row = {"n": n, "leaf": leaf}
+        for name, fn, desc in (("spin", spin.invert, {}), ("lu", spin.invert_lu, {"lu": True})):
+            ms = C._time_ms(lambda: fn(A, leaf=leaf, out=X), reps=3, warm=1)
+            _, fl = spin.plan_describe(n, leaf, **desc)
+            row[name] = {"ms": round(ms, 3), "tflops_2n3": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 3),
+                         "schedule_flops": fl, "rho": spin.residual(A, X), "status": spin.info()}
+            print(f"n={n} {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
+        row["lu_over_spin"] = round(row["lu"]["ms"] / row["spin"]["ms"], 3)
+        rows.append(row)
+        del A, X
+        spin.release()
+        torch.cuda.empty_cache()
+    return rows
+
+
 def cost_model_run():
     """Calibrate the cost model (isolated leaves, nodes and products), then
     predict and time the leaf sweep of U(-1,1) + n I at n = 16384 and the
@@ -360,6 +391,9 @@ def main():
         return
     if args.cost_model:
         print(json.dumps(finite_json({"cost_model": cost_model_run()})), flush=True)
+        return
+    if args.lu_compare:
+        print(json.dumps(finite_json({"lu_compare": lu_compare_run()})), flush=True)
         return
     dev = torch.device("cuda:0")
     seed = args.seed if args.seed is not None else {"spd": 2, "dd": 3, "spdk": 4}[args.kind]

@@ -95,6 +95,20 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
 int spin_invert(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
                 int64_t leaf, spin_stream_t stream);
 
+/* ---- FP64 inversion through a block LU factorisation ---------------------- */
+/* Ainv := A^-1 by the method the paper compares SPIN with (Sec. 5, after Liu
+ * et al.): A = L U without pivoting (as Alg. 1 assumes every leading block
+ * and Schur complement nonsingular), L^-1 and U^-1 by block recursion on the
+ * product kernels, then Ainv = U^-1 L^-1.  Per node: {U12 = Li11 A12,
+ * L21 = A21 Ui11}, S = A22 - L21 U12, {T1 = L21 Li11, T2 = Ui11 U12}, the
+ * recursion on S, {Li21 = -Li22 T1, Ui12 = -T2 Ui22}.  Leaves (order <= leaf
+ * <= 128, else SPIN_E_LEAF) factor and invert in one workgroup.  Arguments,
+ * layout, ownership and status reporting as for spin_invert; the workspace
+ * holds L^-1 and U^-1 (2 n^2 words) besides the recursion's
+ * (spin_plan_ws_elems_lu). */
+int spin_invert_lu(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                   int64_t leaf, spin_stream_t stream);
+
 /* ---- FP64 inversion of a symmetric matrix --------------------------------- */
 /* Ainv := A^-1 for an exactly symmetric A (the positive-definite matrices the
  * paper targets, Sec. 2.1), Alg. 1 specialised: every block the recursion
@@ -220,7 +234,8 @@ size_t spin_server_request_bytes(int64_t n, int64_t leaf, int mode);
  * directly, so C22 = S^-1 and C12 = -III C22, C21 = -C22 II). */
 typedef struct spin_plan_op {
     int kind;        /* 0 = group of block products, 1 = leaf inversion,
-                        2 = transpose, 3 = mirror (spin_plan_describe_spd only) */
+                        2 = transpose, 3 = mirror (spin_plan_describe_spd only),
+                        4 = LU leaf, 5 = zero fill (spin_plan_describe_lu only) */
     int count;       /* products in the group (1 or 2); 1 for a leaf          */
     int level;       /* recursion depth of the node that issues it            */
     int flags;       /* bit q: product q (m == n) forms only its lower triangle;
@@ -234,6 +249,8 @@ typedef struct spin_plan_op {
     /* leaf: out (order L, at d_*[0]) := in^-1 (at a_*[0]); col0 = global column */
     /* transpose: d (n[0] x m[0], at d_*[0]) := a (m[0] x n[0], at a_*[0])^T      */
     /* mirror: the order-m[0] block at d_*[0] gets d[i][j] = d[j][i] for j > i    */
+    /* LU leaf: L^-1 at d_*[0] and U^-1 at c_*[0] of the order-L block at a_*[0]  */
+    /* zero fill: the m[0] x n[0] block at d_*[0]                                  */
     int64_t leaf_order, col0;
 } spin_plan_op;
 
@@ -248,6 +265,11 @@ int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
  * workspace is at most spin_plan_ws_elems(n, leaf) elements. */
 int64_t spin_plan_describe_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
                                spin_plan_op *ops, int64_t cap, double *flops);
+/* The same for spin_invert_lu (kinds 0, 4 and 5; leaf <= 128), with its
+ * workspace size in elements. */
+int64_t spin_plan_describe_lu(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
+                              spin_plan_op *ops, int64_t cap, double *flops);
+int64_t spin_plan_ws_elems_lu(int64_t n, int64_t leaf);
 int64_t spin_plan_ws_elems(int64_t n, int64_t leaf);
 
 /* ---- per-kernel timing (for profiling; forces eager launches) ------------- */

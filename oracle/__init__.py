@@ -69,6 +69,8 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_strassen_inv_spd.restype = ctypes.c_int
     lib.oracle_lu_inv.argtypes = [dp, i64, i64, dp, i64, i64]
     lib.oracle_lu_inv.restype = ctypes.c_int
+    lib.oracle_lu_leaf.argtypes = [dp, i64, i64, dp, i64, dp, i64]
+    lib.oracle_lu_leaf.restype = ctypes.c_int
     lib.oracle_ns_step.argtypes = [dp, i64, i64, dp, i64, dp, i64]
     lib.oracle_ns_step.restype = ctypes.c_int
     lib.oracle_split.argtypes = [i64]
@@ -152,6 +154,17 @@ def lu_inv(a, leaf: int, lib: ctypes.CDLL | None = None):
     x = np.zeros((n, n), dtype=np.float64, order="F")
     info = lib.oracle_lu_inv(_ptr(a), n, max(n, 1), _ptr(x), max(n, 1), int(leaf))
     return x, int(info)
+
+
+def lu_leaf(a, lib: ctypes.CDLL | None = None):
+    """O4's leaf: (L^-1, U^-1, info) of A = L U without pivoting."""
+    lib = lib or load()
+    a = _f64(a)
+    n = a.shape[0]
+    li = np.zeros((n, n), dtype=np.float64, order="F")
+    ui = np.zeros((n, n), dtype=np.float64, order="F")
+    info = lib.oracle_lu_leaf(_ptr(a), n, max(n, 1), _ptr(li), max(n, 1), _ptr(ui), max(n, 1))
+    return li, ui, int(info)
 
 
 def ns_step(a, x, lib: ctypes.CDLL | None = None) -> np.ndarray:

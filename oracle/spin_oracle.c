@@ -324,7 +324,7 @@ int oracle_strassen_inv_spd(const double *A, int64_t n, int64_t lda, double *X, 
  * Li = L^-1 by forward substitution and Ui = U^-1 by back substitution, each
  * written as a full m x m block (zeros in the other triangle).  Returns 0, or
  * the 1-based column of the first zero or non-finite pivot. */
-static int lu_leaf(const double *A, int64_t m, int64_t lda, double *Li, int64_t ldl, double *Ui,
+int oracle_lu_leaf(const double *A, int64_t m, int64_t lda, double *Li, int64_t ldl, double *Ui,
                    int64_t ldu)
 {
     double *F = dalloc(m, m);
@@ -383,7 +383,7 @@ static int lu_rec(const double *A, int64_t m, int64_t lda, double *Li, int64_t l
                   int64_t ldu, int64_t leaf, int64_t col0)
 {
     if (m <= leaf) {
-        int info = lu_leaf(A, m, lda, Li, ldl, Ui, ldu);
+        int info = oracle_lu_leaf(A, m, lda, Li, ldl, Ui, ldu);
         return info > 0 ? (int)(info + col0) : info;
     }
     const int64_t n1 = oracle_split(m), n2 = m - n1;

@@ -122,6 +122,12 @@ def lib() -> ctypes.CDLL:
         L.spin_plan_describe.restype = _i64
         L.spin_plan_describe_spd.argtypes = L.spin_plan_describe.argtypes
         L.spin_plan_describe_spd.restype = _i64
+        L.spin_plan_describe_lu.argtypes = L.spin_plan_describe.argtypes
+        L.spin_plan_describe_lu.restype = _i64
+        L.spin_plan_ws_elems_lu.argtypes = [_i64, _i64]
+        L.spin_plan_ws_elems_lu.restype = _i64
+        L.spin_invert_lu.argtypes = L.spin_invert.argtypes
+        L.spin_invert_lu.restype = ctypes.c_int
         L.spin_invert_spd.argtypes = L.spin_invert.argtypes
         L.spin_invert_spd.restype = ctypes.c_int
         L.spin_plan_ws_elems.argtypes = [_i64, _i64]
@@ -175,14 +181,18 @@ def plan_ws_elems(n: int, leaf: int) -> int:
     return int(lib().spin_plan_ws_elems(int(n), int(leaf)))
 
 
+def plan_ws_elems_lu(n: int, leaf: int) -> int:
+    return int(lib().spin_plan_ws_elems_lu(int(n), int(leaf)))
+
+
 def plan_describe(n: int, leaf: int, lda: int | None = None, ldx: int | None = None,
-                  spd: bool = False):
-    """The recursion schedule (of spin_invert_spd when spd=True) as a list of
-    dicts, plus its flop count."""
+                  spd: bool = False, lu: bool = False):
+    """The recursion schedule (of spin_invert_spd when spd=True, of
+    spin_invert_lu when lu=True) as a list of dicts, plus its flop count."""
     lda = n if lda is None else lda
     ldx = n if ldx is None else ldx
     L = lib()
-    fn = L.spin_plan_describe_spd if spd else L.spin_plan_describe
+    fn = L.spin_plan_describe_lu if lu else L.spin_plan_describe_spd if spd else L.spin_plan_describe
     fl = ctypes.c_double(0)
     cnt = fn(n, lda, ldx, leaf, None, 0, ctypes.byref(fl))
     if cnt < 0:
@@ -201,6 +211,14 @@ def plan_describe(n: int, leaf: int, lda: int | None = None, ldx: int | None = N
                                   d=(o.d_buf[q], o.d_off[q], o.d_ld[q]),
                                   alpha=o.alpha[q], beta=o.beta[q], lower=bool(o.flags >> q & 1)))
             ops.append(dict(kind="products", level=o.level, products=prods))
+        elif o.kind == 4:
+            ops.append(dict(kind="lu_leaf", level=o.level, L=o.leaf_order, col0=o.col0,
+                            src=(o.a_buf[0], o.a_off[0], o.a_ld[0]),
+                            li=(o.d_buf[0], o.d_off[0], o.d_ld[0]),
+                            ui=(o.c_buf[0], o.c_off[0], o.c_ld[0])))
+        elif o.kind == 5:
+            ops.append(dict(kind="fill", level=o.level, m=o.m[0], n=o.n[0],
+                            dst=(o.d_buf[0], o.d_off[0], o.d_ld[0])))
         elif o.kind == 3:
             ops.append(dict(kind="mirror", level=o.level, n=o.m[0],
                             dst=(o.d_buf[0], o.d_off[0], o.d_ld[0])))
@@ -291,6 +309,23 @@ def invert_spd(a, leaf: int, out=None, stream=None):
                                _stream(stream))
     if rc != 0:
         raise SpinError(rc, "spin_invert_spd")
+    return out
+
+
+def invert_lu(a, leaf: int = 128, out=None, stream=None):
+    """A^-1 through a block LU factorisation without pivoting (the paper's
+    comparison method; leaf <= 128), asynchronous on `stream`."""
+    _check_square(a)
+    lda, order = _layout(a)
+    if out is None:
+        out = _empty_like_layout(a, order)
+    ldx, order_x = _layout(out)
+    if order_x != order:
+        raise ValueError("output must have the same memory order as the input")
+    rc = lib().spin_invert_lu(a.data_ptr(), a.shape[0], lda, out.data_ptr(), ldx, int(leaf),
+                              _stream(stream))
+    if rc != 0:
+        raise SpinError(rc, "spin_invert_lu")
     return out
 
 

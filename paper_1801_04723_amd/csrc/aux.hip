@@ -74,6 +74,13 @@ __global__ void __launch_bounds__(256) k_mirror_lower(double *__restrict__ d, in
     }
 }
 
+// 2-D grid-stride zero fill of an (m x n) column-major view.
+__global__ void __launch_bounds__(256) k_fill_zero(double *__restrict__ d, int64_t ld, int64_t m, int64_t n) {
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+            d[i + j * ld] = 0.0;
+}
+
 // Per-block partial sums of squares over whole columns (fixed assignment of
 // columns to blocks and fixed in-block order: the result does not depend on
 // scheduling).
@@ -145,6 +152,14 @@ hipError_t cast_f32_to_f64(const float *src, int64_t lds, double *dst, int64_t l
 hipError_t copy_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
                     int64_t n, hipStream_t s) {
     return convert<double, double>(src, lds, dst, ldd, m, n, s);
+}
+
+hipError_t fill_zero_f64(double *d, int64_t ld, int64_t m, int64_t n, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int64_t bx = (m + 255) / 256;
+    dim3 grid((unsigned)(bx < 64 ? bx : 64), (unsigned)(n < 4096 ? n : 4096));
+    hipLaunchKernelGGL(k_fill_zero, grid, dim3(256), 0, s, d, ld, m, n);
+    return hipGetLastError();
 }
 
 hipError_t mirror_lower_f64(double *d, int64_t ld, int64_t n, hipStream_t s) {

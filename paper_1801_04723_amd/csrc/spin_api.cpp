@@ -170,7 +170,79 @@ void plan_node_spd(Plan &P, Ref in, Ref out, int64_t m, int64_t wsoff, int level
     push_mirror(P, level, C11, n1);
 }
 
+// Inversion through a block LU factorisation without pivoting (the method the
+// paper compares SPIN with, Sec. 5): the recursion produces Li = L^-1 and
+// Ui = U^-1 into two full order-n workspace blocks that start zeroed,
+//   (Li11, Ui11) = rec(A11);  {U12 = Li11 A12, L21 = A21 Ui11};
+//   S = A22 - L21 U12;  {T1 = L21 Li11, T2 = Ui11 U12};  (Li22, Ui22) = rec(S);
+//   {Li21 = -Li22 T1, Ui12 = -T2 Ui22},
+// and X = Ui Li closes the schedule.  Leaves factor and invert in one kernel.
+void plan_node_lu(Plan &P, Ref in, Ref li, Ref ui, int64_t m, int64_t wsoff, int level,
+                  int64_t col0) {
+    if (m <= P.leaf) {
+        POp op{};
+        op.kind = 4;
+        op.count = 1;
+        op.level = level;
+        op.in = in;
+        op.out = li;
+        op.out2 = ui;
+        op.L = m;
+        op.col0 = col0;
+        P.ops.push_back(op);
+        P.flops += 4.0 / 3.0 * m * m * m;  // LU and two triangular inverses
+        return;
+    }
+    const int64_t n1 = split_order(m), n2 = m - n1;
+    const Ref A12 = sub(in, 0, n1), A21 = sub(in, n1, 0), A22 = sub(in, n1, n1);
+    const Ref Li11 = sub(li, 0, 0), Li21 = sub(li, n1, 0), Li22 = sub(li, n1, n1);
+    const Ref Ui11 = sub(ui, 0, 0), Ui12 = sub(ui, 0, n1), Ui22 = sub(ui, n1, n1);
+    plan_node_lu(P, sub(in, 0, 0), Li11, Ui11, n1, wsoff, level + 1, col0);
+    const Ref U12{BUF_WS, wsoff, n1};
+    const Ref L21{BUF_WS, wsoff + n1 * n2, n2};
+    const Ref S{BUF_WS, wsoff + 2 * n1 * n2, n2};
+    const Ref T1{BUF_WS, wsoff + 2 * n1 * n2 + n2 * n2, n2};
+    const Ref T2{BUF_WS, wsoff + 3 * n1 * n2 + n2 * n2, n1};
+    const int64_t next = wsoff + 4 * n1 * n2 + n2 * n2;
+    P.ws_elems = std::max(P.ws_elems, next);
+    const Ref none{BUF_WS, 0, 1};
+    const PGemm g_u12{Li11, A12, none, U12, n1, n2, n1, 1.0, 0.0, 0};
+    const PGemm g_l21{A21, Ui11, none, L21, n2, n1, n1, 1.0, 0.0, 0};
+    push_products(P, level, g_u12, &g_l21);
+    push_products(P, level, PGemm{L21, U12, A22, S, n2, n2, n1, -1.0, 1.0, 0}, nullptr);
+    const PGemm g_t1{L21, Li11, none, T1, n2, n1, n1, 1.0, 0.0, 0};
+    const PGemm g_t2{Ui11, U12, none, T2, n1, n2, n1, 1.0, 0.0, 0};
+    push_products(P, level, g_t1, &g_t2);
+    plan_node_lu(P, S, Li22, Ui22, n2, next, level + 1, col0 + n1);
+    const PGemm g_li21{Li22, T1, none, Li21, n2, n1, n2, -1.0, 0.0, 0};
+    const PGemm g_ui12{T2, Ui22, none, Ui12, n1, n2, n2, -1.0, 0.0, 0};
+    push_products(P, level, g_li21, &g_ui12);
+}
+
 }  // namespace
+
+Plan make_plan_lu(int64_t n, int64_t lda, int64_t ldx, int64_t leaf) {
+    Plan P;
+    P.n = n;
+    P.lda = lda;
+    P.ldx = ldx;
+    P.leaf = leaf;
+    const Ref LI{BUF_WS, 0, n}, UI{BUF_WS, n * n, n};
+    P.ws_elems = 2 * n * n;
+    for (const Ref &r : {LI, UI}) {
+        POp z{};
+        z.kind = 5;
+        z.count = 1;
+        z.out = r;
+        z.tm = n;
+        z.tn = n;
+        P.ops.push_back(z);
+    }
+    plan_node_lu(P, Ref{BUF_A, 0, lda}, LI, UI, n, 2 * n * n, 0, 0);
+    const Ref none{BUF_WS, 0, 1};
+    push_products(P, 0, PGemm{UI, LI, none, Ref{BUF_X, 0, ldx}, n, n, n, 1.0, 0.0, 0}, nullptr);
+    return P;
+}
 
 Plan make_plan_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf) {
     Plan P;
@@ -358,6 +430,25 @@ hipError_t run_plan(const Plan &P, const Exec &E) {
                                          op.tn, E.s);
             if (tr) trace_cb(&ctx, li, 1);
             if (e != hipSuccess) return e;
+        } else if (op.kind == 4) {
+            if (E.dt != kF64) return hipErrorInvalidValue;
+            const double Ld = (double)op.L;
+            LaunchInfo li{"lu_leaf", 4.0 / 3.0 * Ld * Ld * Ld, 24.0 * Ld * Ld};
+            if (tr) trace_cb(&ctx, li, 0);
+            hipError_t e = lu_leaf_launch(static_cast<const double *>(at(E, op.in)), op.in.ld,
+                                          static_cast<double *>(at(E, op.out)), op.out.ld,
+                                          static_cast<double *>(at(E, op.out2)), op.out2.ld, op.L,
+                                          op.col0, E.status, E.s);
+            if (tr) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
+        } else if (op.kind == 5) {
+            if (E.dt != kF64) return hipErrorInvalidValue;
+            LaunchInfo li{"fill", 0.0, 8.0 * (double)op.tm * (double)op.tn};
+            if (tr) trace_cb(&ctx, li, 0);
+            hipError_t e = fill_zero_f64(static_cast<double *>(at(E, op.out)), op.out.ld, op.tm,
+                                         op.tn, E.s);
+            if (tr) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
         } else if (op.kind == 3) {
             if (E.dt != kF64) return hipErrorInvalidValue;
             LaunchInfo li{"mirror", 0.0, 8.0 * (double)op.tm * (double)op.tm};
@@ -496,6 +587,32 @@ int spin_invert_spd(const double *A, int64_t n, int64_t lda, double *Ainv, int64
         return run_plan(P, Eq);
     };
     return run_maybe_graph(std::make_tuple(2, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
+                                           (void *)w->base, 0),
+                           s, body);
+}
+
+int spin_invert_lu(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                   int64_t leaf, spin_stream_t stream) {
+    int rc = validate(A, n, lda, Ainv, ldx, leaf);
+    if (rc) return rc;
+    if (leaf > kLuLeafMax) return SPIN_E_LEAF;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Plan P = make_plan_lu(n, lda, ldx, leaf);
+    Layout L = layout_for(n, leaf, SPIN_FP64, P.ws_elems, 0);
+    Workspace *w = nullptr;
+    rc = ws_acquire(s, L.total, &w);
+    if (rc) return rc;
+    Exec E{s, {(char *)A, (char *)Ainv, w->base + L.rec_off}, 8, kF64, status_ptr(w),
+           w->base + L.leaf_off};
+    auto body = [&](hipStream_t qs) -> hipError_t {
+        Exec Eq = E;
+        Eq.s = qs;
+        hipError_t e = status_reset(Eq.status, 2, qs);
+        if (e != hipSuccess) return e;
+        return run_plan(P, Eq);
+    };
+    return run_maybe_graph(std::make_tuple(3, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
                                            (void *)w->base, 0),
                            s, body);
 }
@@ -750,6 +867,24 @@ int64_t describe_plan(const Plan &P, spin_plan_op *ops, int64_t cap, double *flo
                 o.beta[q] = g.beta;
                 if (g.lower) o.flags |= 1 << q;
             }
+        } else if (op.kind == 4) {
+            o.a_buf[0] = op.in.buf;
+            o.a_off[0] = op.in.off;
+            o.a_ld[0] = op.in.ld;
+            o.d_buf[0] = op.out.buf;
+            o.d_off[0] = op.out.off;
+            o.d_ld[0] = op.out.ld;
+            o.c_buf[0] = op.out2.buf;
+            o.c_off[0] = op.out2.off;
+            o.c_ld[0] = op.out2.ld;
+            o.leaf_order = op.L;
+            o.col0 = op.col0;
+        } else if (op.kind == 5) {
+            o.m[0] = op.tm;
+            o.n[0] = op.tn;
+            o.d_buf[0] = op.out.buf;
+            o.d_off[0] = op.out.off;
+            o.d_ld[0] = op.out.ld;
         } else if (op.kind == 3) {
             o.m[0] = op.tm;
             o.n[0] = op.tm;
@@ -791,6 +926,20 @@ int64_t spin_plan_describe(int64_t n, int64_t lda, int64_t ldx, int64_t leaf, sp
     if (leaf < 1 || leaf > SPIN_MAX_LEAF) return SPIN_E_LEAF;
     if (cap > 0 && !ops) return SPIN_E_NULL;
     return describe_plan(make_plan(n, lda, ldx, leaf), ops, cap, flops);
+}
+
+int64_t spin_plan_describe_lu(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,
+                              spin_plan_op *ops, int64_t cap, double *flops) {
+    if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
+    if (lda < n || ldx < n) return SPIN_E_LD;
+    if (leaf < 1 || leaf > kLuLeafMax) return SPIN_E_LEAF;
+    if (cap > 0 && !ops) return SPIN_E_NULL;
+    return describe_plan(make_plan_lu(n, lda, ldx, leaf), ops, cap, flops);
+}
+
+int64_t spin_plan_ws_elems_lu(int64_t n, int64_t leaf) {
+    if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > kLuLeafMax) return SPIN_E_N;
+    return make_plan_lu(n, n, n, leaf).ws_elems;
 }
 
 int64_t spin_plan_describe_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf,

@@ -101,6 +101,15 @@ hipError_t transpose_f64(const double *src, int64_t lds, double *dst, int64_t ld
                          int64_t n, hipStream_t s);
 // In place on an order-n view: d[i][j] = d[j][i] for j > i.
 hipError_t mirror_lower_f64(double *d, int64_t ld, int64_t n, hipStream_t s);
+// d (m x n, ld) = 0, by a kernel (so that it can be captured in a graph).
+hipError_t fill_zero_f64(double *d, int64_t ld, int64_t m, int64_t n, hipStream_t s);
+
+// Leaf of the block-LU inversion (lu.hip): for an order-L block (L <=
+// kLuLeafMax) A = L U without pivoting; Li = L^-1 and Ui = U^-1 written as
+// full blocks.  A zero or non-finite pivot lowers *status to col0 + k + 1.
+constexpr int kLuLeafMax = 128;
+hipError_t lu_leaf_launch(const double *A, int64_t lda, double *Li, int64_t ldl, double *Ui,
+                          int64_t ldu, int64_t L, int64_t col0, int *status, hipStream_t s);
 // Sum of squares of an (m x n) FP64 view, deterministic two-pass reduction:
 // partials (>= frob_partials_count(m, n) doubles) then one block writes *out.
 int frob_partials_count(int64_t m, int64_t n);

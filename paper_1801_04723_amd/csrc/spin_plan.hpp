@@ -31,14 +31,16 @@ struct PGemm {
 };
 
 // One step: a group of independent products (kind 0), a leaf (kind 1), a
-// transpose (kind 2: out (tn x tm) := in (tm x tn)^T) or a mirror (kind 3:
-// the lower triangle of the order-tm block `out` copied onto its upper one).
+// transpose (kind 2: out (tn x tm) := in (tm x tn)^T), a mirror (kind 3:
+// the lower triangle of the order-tm block `out` copied onto its upper one),
+// an LU leaf (kind 4: out := L^-1 and out2 := U^-1 of the order-L block in)
+// or a zero fill (kind 5: the tm x tn block out).
 struct POp {
     int kind;
     int count;
     int level;
     PGemm g[2];
-    Ref in, out;
+    Ref in, out, out2;
     int64_t L, col0;
     int64_t tm, tn;
 };
@@ -89,5 +91,7 @@ int64_t split_order(int64_t m);
 Plan make_plan(int64_t n, int64_t lda, int64_t ldx, int64_t leaf);
 // The same for a symmetric matrix: four products and one transpose per node.
 Plan make_plan_spd(int64_t n, int64_t lda, int64_t ldx, int64_t leaf);
+// Inversion through a block LU factorisation (the comparison method).
+Plan make_plan_lu(int64_t n, int64_t lda, int64_t ldx, int64_t leaf);
 
 }  // namespace spin

@@ -138,12 +138,13 @@ def test_split_rule_matches_oracle(m):
     assert n1 == oracle.split(m)
 
 
-def _run_schedule_on_cpu(A, leaf, spd=False):
-    """Replay the library's schedule with the oracle's GEMM and GJ."""
+def _run_schedule_on_cpu(A, leaf, spd=False, lu=False):
+    """Replay the library's schedule with the oracle's GEMM and leaf routines."""
     n = A.shape[0]
-    ops, _ = S.plan_describe(n, leaf, spd=spd)
+    ops, _ = S.plan_describe(n, leaf, spd=spd, lu=lu)
+    ws = S.plan_ws_elems_lu(n, leaf) if lu else S.plan_ws_elems(n, leaf)
     bufs = [np.asfortranarray(A).ravel(order="F").copy(),
-            np.zeros(n * n), np.zeros(max(S.plan_ws_elems(n, leaf), 1))]
+            np.full(n * n, np.nan), np.full(max(ws, 1), np.nan)]
 
     def view(ref, r, c):
         b, off, ld = ref
@@ -158,6 +159,14 @@ def _run_schedule_on_cpu(A, leaf, spd=False):
             assert info == 0
             dst = view(o["dst"], L, L)
             dst[...] = x
+        elif o["kind"] == "lu_leaf":
+            L = o["L"]
+            li, ui, info = oracle.lu_leaf(np.array(view(o["src"], L, L)))
+            assert info == 0
+            view(o["li"], L, L)[...] = li
+            view(o["ui"], L, L)[...] = ui
+        elif o["kind"] == "fill":
+            view(o["dst"], o["m"], o["n"])[...] = 0.0
         elif o["kind"] == "transpose":
             src = np.array(view(o["src"], o["m"], o["n"]))
             view(o["dst"], o["n"], o["m"])[...] = src.T
@@ -263,6 +272,46 @@ def test_spd_workspace_within_plain(n, leaf):
             if buf == 2:
                 top = max(top, off + (c - 1) * ld + r)
     assert top <= ws
+
+
+@pytest.mark.parametrize("gen,n,leaf", [("dd", 256, 64), ("spd", 128, 16), ("dd", 300, 64), ("dd", 64, 64),
+                                        ("dd", 130, 32)])
+def test_lu_schedule_replay_equals_oracle_bitwise(gen, n, leaf):
+    """The block-LU schedule of spin_invert_lu, replayed with the oracle's
+    product and LU-leaf routines (every buffer starting as NaN), is O4 bit for
+    bit: every block it reads has been written, the zeros included."""
+    A = W.diag_dominant(n, 1) if gen == "dd" else W.spd_gram(n, 2)
+    X = _run_schedule_on_cpu(A, leaf, lu=True)
+    ref, info = oracle.lu_inv(A, leaf)
+    assert info == 0
+    assert np.array_equal(X, ref)
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (8192, 128), (300, 64), (1, 1)])
+def test_lu_plan_structure(n, leaf):
+    ops, fl = S.plan_describe(n, leaf, lu=True)
+    plain, _ = S.plan_describe(n, leaf)
+    assert [o["kind"] for o in ops[:2]] == ["fill", "fill"]
+    leaves = [(o["L"], o["col0"]) for o in ops if o["kind"] == "lu_leaf"]
+    assert leaves == [(o["L"], o["col0"]) for o in plain if o["kind"] == "leaf"]
+    internal = sum(1 for o in plain if o["kind"] == "products") // 4
+    prods = [o for o in ops if o["kind"] == "products"]
+    assert len(prods) == 4 * internal + 1  # three pairs and S per node, then X = Ui Li
+    last = prods[-1]["products"][0]
+    assert (last["m"], last["n"], last["k"]) == (n, n, n) and last["d"][0] == 1
+    expect = sum(4 / 3 * L ** 3 for L, _ in leaves) + sum(
+        2.0 * p["m"] * p["n"] * p["k"] for o in prods for p in o["products"])
+    assert abs(fl - expect) <= 1e-9 * fl
+
+
+def test_lu_argument_validation():
+    L = S.lib()
+    p = ctypes.c_void_p
+    A, X, s = p(0x10000000), p(0x20000000), p(0)
+    assert L.spin_invert_lu(None, 4, 4, X, 4, 2, s) == -1
+    assert L.spin_invert_lu(A, 8, 8, X, 8, 129, s) == -4  # LU leaves stop at 128
+    assert L.spin_invert_lu(A, 8, 8, p(0x10000000 + 8 * 60), 8, 2, s) == -5
+    assert L.spin_plan_describe_lu(8, 8, 8, 129, None, 0, None) == -4
 
 
 # ------------------------------------------------------- server admission (CPU)
