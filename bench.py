@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--serve-seconds", type=float, default=10.0,
                    help="length of the open-loop serving run (0 disables it)")
     p.add_argument("--serve-rate", type=float, default=200.0, help="serving arrival rate, req/s")
+    p.add_argument("--serve-plain", action="store_true",
+                   help="serve SPD FP64 requests on the plain schedule instead of the symmetric one")
     p.add_argument("--mixed-n", type=int, default=16384,
                    help="order of the mixed-precision vs FP64 comparison (0 disables it)")
     p.add_argument("--mixed-leaf", type=int, default=256)
@@ -118,19 +120,22 @@ def cpu_baseline(kind: str, n: int, leaf: int, seed: int, budget_s: float):
     }
 
 
-def serving(rate: float, seconds: float):
+def serving(rate: float, seconds: float, symmetric: bool = True):
     """Open-loop serving run: Poisson arrivals at `rate` for `seconds`, orders
     log-uniform in [64, 4096] padded to 64, half diagonally dominant and half
     SPD (kappa log-uniform in [10, 1e4]), 70% mixed precision with 2 Newton
-    steps and 30% FP64, leaf 128; orders below 512, from 512 to 2047 and from
-    2048 up are served by three server lanes on three streams; p50/p99
-    latency from arrival to completion, TFLOP/s from 2n^3 per request."""
+    steps and 30% FP64 (its SPD requests on the symmetric schedule), leaf
+    128; orders below 512, from 512 to 2047 and from 2048 up are served by
+    three server lanes on three streams; p50/p99 latency from arrival to
+    completion, TFLOP/s from 2n^3 per request (the plain method's count, also
+    for symmetric requests)."""
     import workloads as W
     from paper_1801_04723_amd import serve
     trace = W.serving_trace(rate=rate, duration=seconds, seed=5)
-    st = serve.run_trace(trace, leaf=128, ns_steps=2, split_n=[512, 2048])
+    st = serve.run_trace(trace, leaf=128, ns_steps=2, split_n=[512, 2048], symmetric=symmetric)
     st["workload"] = (f"Poisson {rate:g} req/s for {seconds:g} s, n log-uniform 64..4096 (x64), "
-                      "50% diag-dominant / 50% SPD, 70% mixed FP32+2 Newton / 30% FP64, leaf 128; "
+                      "50% diag-dominant / 50% SPD, 70% mixed FP32+2 Newton / 30% FP64 "
+                      f"({'SPD ones on the symmetric schedule' if symmetric else 'plain schedule'}), leaf 128; "
                       "three server lanes on three streams (n < 512, 512 <= n < 2048, n >= 2048)")
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
 
@@ -481,7 +486,7 @@ def main():
     if args.mode == "fp64" and not args.spd and args.kind != "dd" and not args.no_spd_variant:
         out["spd_variant"] = spd_variant(dA, n, leaf, args.steps, args.warmup, ms)
     if args.serve_seconds > 0:
-        out["serving"] = serving(args.serve_rate, args.serve_seconds)
+        out["serving"] = serving(args.serve_rate, args.serve_seconds, not args.serve_plain)
     if args.mixed_n > 0:
         del dA, dX
         spin.release()

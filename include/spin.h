@@ -85,6 +85,11 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
                               hi*hi + lo*hi + hi*lo accumulated in FP32
                               (about 16 significant bits per operand); needs
                               one refinement step more than SPIN_MIXED_FP32   */
+/* Schedule flag for the batched and serving entry points only: a request of
+ * mode SPIN_FP64 | SPIN_SYMMETRIC runs the symmetric schedule of
+ * spin_invert_spd (A must be exactly symmetric) and its result is bit for bit
+ * spin_invert_spd's.  Any other combination with this flag is SPIN_E_MODE. */
+#define SPIN_SYMMETRIC 16
 
 /* ---- FP64 inversion ------------------------------------------------------- */
 /* Ainv (n x n, ldx) := A^-1 for A (n x n, lda), FP64 throughout.
@@ -187,12 +192,13 @@ void spin_release(void);
 
 /* ---- batched inversion and continuous batching ---------------------------- */
 /* Inverts `count` independent matrices (each column-major, its own order n[i]
- * and leading dimensions; mode[i] = SPIN_FP64 or one of the mixed modes with
- * `ns_steps` refinement steps) with cross-request batching: at each step the
- * block products of all requests run in grouped matrix-core launches and
- * their leaves in one batched leaf launch.  Every request's result is bit for
- * bit the one spin_invert / spin_invert_mixed would give it alone.  Waits for
- * the stream; info[i] (optional) receives request i's numerical status. */
+ * and leading dimensions; mode[i] = SPIN_FP64, SPIN_FP64 | SPIN_SYMMETRIC or
+ * one of the mixed modes with `ns_steps` refinement steps) with cross-request
+ * batching: at each step the block products of all requests run in grouped
+ * matrix-core launches and their leaves in one batched leaf launch.  Every
+ * request's result is bit for bit the one spin_invert / spin_invert_spd /
+ * spin_invert_mixed would give it alone.  Waits for the stream; info[i]
+ * (optional) receives request i's numerical status. */
 int spin_invert_batch(int64_t count, const double *const *A, const int64_t *n,
                       const int64_t *lda, double *const *Ainv, const int64_t *ldx,
                       const int *mode, int64_t leaf, int ns_steps, int *info,
@@ -209,8 +215,8 @@ int spin_invert_batch(int64_t count, const double *const *A, const int64_t *n,
 typedef struct spin_server spin_server;
 spin_server *spin_server_create(size_t pool_bytes, int max_active, int64_t leaf, int ns_steps);
 void spin_server_destroy(spin_server *srv);
-/* Queues one request (returns 0, or SPIN_E_* when the arguments are invalid or
- * the request could never fit in the pool). */
+/* Queues one request, mode as for spin_invert_batch (returns 0, or SPIN_E_*
+ * when the arguments are invalid or the request could never fit in the pool). */
 int spin_server_submit(spin_server *srv, const double *A, int64_t n, int64_t lda, double *Ainv,
                        int64_t ldx, int mode, int64_t tag);
 /* Host only: admits queued requests that fit (returns how many). */
@@ -225,7 +231,8 @@ int spin_server_tick(spin_server *srv, spin_stream_t stream);
  * A status of SPIN_E_HIP means they could not be read. */
 int64_t spin_server_poll(spin_server *srv, int64_t *tags, int *info, int64_t cap);
 int spin_server_stats(spin_server *srv, int64_t *queued, int64_t *active, size_t *pool_used);
-/* Pool bytes one request of order n needs (0 for invalid arguments). */
+/* Pool bytes one request of order n and mode `mode` (SPIN_SYMMETRIC allowed
+ * as above) needs (0 for invalid arguments). */
 size_t spin_server_request_bytes(int64_t n, int64_t leaf, int mode);
 
 /* ---- schedule introspection (host only, no GPU needed) -------------------- */

@@ -6,7 +6,9 @@
 // of Alg. 1 in S-form, Newton refinement).  A tick takes the next step of
 // every active request: block products from all requests go into grouped
 // matrix-core launches (one grid per kernel configuration), whole leaves into
-// one batched leaf launch, and the small auxiliary kernels run as they come.
+// one batched leaf launch, and the small auxiliary kernels (status resets,
+// conversions, norms, and the symmetric schedule's transposes and mirrors)
+// run as they come.
 // Steps of one request stay in order (one product/leaf step per request per
 // tick, all launched on one stream), and every kernel computes each
 // product/leaf exactly as it does alone, so a request's result is bit for bit
@@ -80,7 +82,11 @@ class PoolAllocator {
 
 // --------------------------------------------------------------- steps ----
 enum StepKind { STEP_GEMM = 0, STEP_LEAF = 1, STEP_AUX = 2 };
-enum AuxOp { AUX_RESET, AUX_CAST_IN, AUX_WIDEN, AUX_FROB, AUX_NSCHECK };
+enum AuxOp { AUX_RESET, AUX_CAST_IN, AUX_WIDEN, AUX_FROB, AUX_NSCHECK, AUX_TRANSPOSE, AUX_MIRROR };
+
+// FP64 request on the symmetric schedule of spin_invert_spd.
+constexpr int kModeSym = SPIN_FP64 | SPIN_SYMMETRIC;
+bool server_mode(int mode) { return is_mode(mode) || mode == kModeSym; }
 
 struct Step {
     int kind;
@@ -123,6 +129,7 @@ Step aux_step(int op) {
 }
 
 // gdt: product flavour of the plan's products; leaves use its storage type.
+// Transposes and mirrors (FP64 plans only) become auxiliary steps.
 void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, int *status,
                     void *leaf_scratch, std::vector<Step> &out) {
     for (const POp &op : P.ops) {
@@ -133,6 +140,17 @@ void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, in
             st.kind = STEP_GEMM;
             st.nprob = op.count;
             for (int q = 0; q < op.count; ++q) st.prob[q] = make_prob(base, es, op.g[q]);
+        } else if (op.kind == 2 || op.kind == 3) {
+            st.kind = STEP_AUX;
+            st.aux = op.kind == 2 ? AUX_TRANSPOSE : AUX_MIRROR;
+            if (op.kind == 2) {
+                st.src = base[op.in.buf] + (size_t)op.in.off * es;
+                st.lds = op.in.ld;
+            }
+            st.dst = base[op.out.buf] + (size_t)op.out.off * es;
+            st.ldd = op.out.ld;
+            st.m = op.tm;
+            st.n = op.tn;
         } else {
             st.kind = STEP_LEAF;
             st.leaf = LeafItem{base[op.in.buf] + (size_t)op.in.off * es, op.in.ld,
@@ -144,8 +162,8 @@ void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, in
     }
 }
 
-// The steps of one request: the same launches spin_invert / spin_invert_mixed
-// make, in the same order, with the request's own workspace.
+// The steps of one request: the same launches spin_invert / spin_invert_spd /
+// spin_invert_mixed make, in the same order, with the request's own workspace.
 void build_steps(Request &r, int64_t leaf, int ns_steps) {
     const int64_t n = r.n;
     char *w = r.ws;
@@ -155,8 +173,9 @@ void build_steps(Request &r, int64_t leaf, int ns_steps) {
     Step rs = aux_step(AUX_RESET);
     rs.status = status;
     r.steps.push_back(rs);
-    if (r.mode == SPIN_FP64) {
-        Plan P = make_plan(n, r.lda, r.ldx, leaf);
+    if (r.mode == SPIN_FP64 || r.mode == kModeSym) {
+        Plan P = r.mode == kModeSym ? make_plan_spd(n, r.lda, r.ldx, leaf)
+                                    : make_plan(n, r.lda, r.ldx, leaf);
         Layout L = layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf);
         char *const base[3] = {(char *)r.A, (char *)r.X, w + L.rec_off};
         add_plan_steps(P, base, 8, kF64, status, w + L.leaf_off, r.steps);
@@ -222,6 +241,10 @@ hipError_t run_aux(const Step &s, hipStream_t st) {
     case AUX_FROB:
         return frob2(static_cast<const double *>(s.src), s.lds, s.m, s.n, s.partials, s.norms, st);
     case AUX_NSCHECK: return ns_check(s.norms, s.j, s.status, st);
+    case AUX_TRANSPOSE:
+        return transpose_f64(static_cast<const double *>(s.src), s.lds, static_cast<double *>(s.dst),
+                             s.ldd, s.m, s.n, st);
+    case AUX_MIRROR: return mirror_lower_f64(static_cast<double *>(s.dst), s.ldd, s.m, st);
     }
     return hipErrorInvalidValue;
 }
@@ -251,6 +274,10 @@ struct spin_server {
 namespace {
 
 size_t request_bytes(int64_t n, int64_t leaf, int mode) {
+    if (mode == kModeSym) {
+        Plan P = make_plan_spd(n, n, n, leaf);
+        return layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf).total;
+    }
     Plan P = make_plan(n, n, n, leaf);
     return layout_for(n, leaf, mode, P.ws_elems, P.max_leaf).total;
 }
@@ -306,7 +333,7 @@ int spin_server_submit(spin_server *s, const double *A, int64_t n, int64_t lda, 
     if (!s || !A || !Ainv) return SPIN_E_NULL;
     if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
     if (lda < n || ldx < n) return SPIN_E_LD;
-    if (!is_mode(mode)) return SPIN_E_MODE;
+    if (!server_mode(mode)) return SPIN_E_MODE;
     const char *a0 = reinterpret_cast<const char *>(A), *x0 = reinterpret_cast<const char *>(Ainv);
     const char *a1 = a0 + ((size_t)(n - 1) * lda + n) * 8, *x1 = x0 + ((size_t)(n - 1) * ldx + n) * 8;
     if (a0 < x1 && x0 < a1) return SPIN_E_ALIAS;
@@ -436,7 +463,7 @@ int spin_server_stats(spin_server *s, int64_t *queued, int64_t *active, size_t *
 
 size_t spin_server_request_bytes(int64_t n, int64_t leaf, int mode) {
     if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > SPIN_MAX_LEAF) return 0;
-    if (!is_mode(mode)) return 0;
+    if (!server_mode(mode)) return 0;
     return al256(request_bytes(n, leaf, mode));
 }
 
@@ -451,7 +478,7 @@ int spin_invert_batch(int64_t count, const double *const *A, const int64_t *n, c
     size_t total = 0;
     for (int64_t i = 0; i < count; ++i) {
         if (n[i] < 1 || n[i] > SPIN_MAX_N) return SPIN_E_N;
-        if (!is_mode(mode[i])) return SPIN_E_MODE;
+        if (!server_mode(mode[i])) return SPIN_E_MODE;
         total += al256(request_bytes(n[i], leaf, mode[i]));
     }
     spin_server *s = spin_server_create(total, (int)count, leaf, ns_steps);

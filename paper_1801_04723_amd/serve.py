@@ -20,7 +20,7 @@ import collections
 import math
 import time
 
-from . import FP64, MIXED_FP32, Server, server_request_bytes
+from . import FP64, MIXED_FP32, SYMMETRIC, Server, server_request_bytes
 
 KAPPA_BUCKETS = (10 ** 1.5, 10 ** 2.5, 10 ** 3.5)
 
@@ -61,7 +61,7 @@ def percentile(xs, p):
 
 def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 << 30,
               max_active: int = 64, max_ticks_in_flight: int = 64, pool: MatrixPool | None = None,
-              split_n=None):
+              split_n=None, symmetric: bool = False):
     """Serves `trace` (list of dicts with t, n, kind, kappa, mixed) and returns
     latency / throughput statistics.
 
@@ -69,7 +69,10 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
     into lanes by order; each lane is its own server on its own stream, with
     the pool divided evenly.  The long step sequences of large requests and
     the many short steps of small ones then run side by side instead of
-    taking turns in one stream; each request's result is the same either way."""
+    taking turns in one stream; each request's result is the same either way.
+
+    symmetric: FP64 requests for SPD matrices (exactly symmetric inputs) run
+    the symmetric schedule (mode FP64 | SYMMETRIC), about half the flops."""
     import torch
     pool = pool or MatrixPool()
     # materialise the inputs before the clock starts
@@ -96,7 +99,13 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
             a = pool.get(r["n"], r["kind"], r["kappa"])
             x = torch.empty_like(a)
             lane = sum(1 for b in bounds if r["n"] >= b)
-            lanes[lane][0].submit(a, x, MIXED_FP32 if r["mixed"] else FP64, tag=nxt)
+            if r["mixed"]:
+                mode = MIXED_FP32
+            elif symmetric and r["kind"] != "dd":
+                mode = FP64 | SYMMETRIC
+            else:
+                mode = FP64
+            lanes[lane][0].submit(a, x, mode, tag=nxt)
             outs[nxt] = x
             nxt += 1
         busy = False
@@ -138,4 +147,5 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
         "max_active": max_active,
         "lanes": len(lanes),
         "split_n": bounds,
+        "symmetric": bool(symmetric),
     }

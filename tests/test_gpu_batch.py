@@ -31,12 +31,15 @@ def _dev(torch, a):
 def _solo(S, a, mode, leaf, ns_steps):
     if mode == "fp64":
         return S.invert(a, leaf=leaf)
+    if mode == "fp64_sym":
+        return S.invert_spd(a, leaf=leaf)
     return S.invert_mixed(a, leaf=leaf, mode=mode, ns_steps=ns_steps)
 
 
 REQS = [(256, "dd", "fp64"), (320, "spd", "fp32"), (64, "dd", "fp64"), (512, "spdk", "fp32"),
         (130, "dd", "fp64"), (1024, "spd", "fp64"), (192, "spdk", "fp32"), (40, "dd", "fp32"),
-        (384, "dd", "bf16x3"), (200, "dd", "bf16")]
+        (384, "dd", "bf16x3"), (200, "dd", "bf16"), (512, "spd", "fp64_sym"),
+        (200, "spdk", "fp64_sym"), (64, "spd", "fp64_sym")]
 
 
 def _mat(n, kind, seed):
@@ -104,14 +107,16 @@ def test_singular_request_does_not_disturb_others(torch_cuda):
     assert torch.equal(outs[2], S.invert_mixed(good[1], leaf=64, ns_steps=2))
 
 
-@pytest.mark.parametrize("split", [None, [128, 256]])
-def test_serving_loop_short_trace(torch_cuda, split):
-    """One lane, and three lanes on three streams split by order."""
+@pytest.mark.parametrize("split,sym", [(None, False), ([128, 256], False), ([128, 256], True)])
+def test_serving_loop_short_trace(torch_cuda, split, sym):
+    """One lane, and three lanes on three streams split by order (SPD FP64
+    requests on the plain or the symmetric schedule)."""
     import paper_1801_04723_amd.serve as serve
     import workloads as W
     trace = W.serving_trace(rate=100.0, duration=0.5, seed=11, n_max=512)
     stats = serve.run_trace(trace, leaf=64, ns_steps=2, pool_bytes=4 << 30, max_active=16,
-                            split_n=split)
+                            split_n=split, symmetric=sym)
+    assert stats["symmetric"] == sym
     assert stats["requests"] == len(trace) > 10
     assert stats["status_counts"] == {0: len(trace)}
     assert stats["p50_ms"] <= stats["p99_ms"] <= stats["max_ms"]

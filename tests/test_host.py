@@ -361,3 +361,28 @@ def test_server_slot_cap_and_validation():
     tiny.close()
     assert L.spin_server_create(0, 4, 64, 2) is None
     assert L.spin_invert_batch(-1, None, None, None, None, None, None, 64, 2, None, None) == -7
+
+
+def test_server_symmetric_mode_validation():
+    """FP64 | SYMMETRIC is a server/batch mode with the symmetric schedule's
+    footprint; the flag with a mixed mode is rejected everywhere."""
+    L = S.lib()
+    leaf = 64
+    for n in (1, 64, 200, 1024):
+        sym = S.server_request_bytes(n, leaf, "fp64_sym")
+        assert 0 < sym <= S.server_request_bytes(n, leaf, "fp64")
+    bad = S.MIXED_FP32 | S.SYMMETRIC
+    assert S.server_request_bytes(256, leaf, bad) == 0
+    assert S.server_request_bytes(256, leaf, S.SYMMETRIC | 32) == 0
+    srv = S.Server(1 << 30, max_active=2, leaf=leaf)
+    h = srv._h
+    assert L.spin_server_submit(h, _fake(0), 256, 256, _fake(1), 256, S.FP64 | S.SYMMETRIC, 0) == 0
+    assert L.spin_server_submit(h, _fake(2), 256, 256, _fake(3), 256, bad, 1) == -6
+    assert srv.admit() == 1
+    assert srv.stats()["pool_used"] == S.server_request_bytes(256, leaf, "fp64_sym")
+    srv.close()
+    i64 = ctypes.c_int64 * 1
+    ptrs = ctypes.c_void_p * 1
+    rc = L.spin_invert_batch(1, ptrs(_fake(4)), i64(256), i64(256), ptrs(_fake(5)), i64(256),
+                             (ctypes.c_int * 1)(bad), leaf, 2, None, None)
+    assert rc == -6
