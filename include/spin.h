@@ -246,7 +246,10 @@ typedef struct spin_plan_op {
     int count;       /* products in the group (1 or 2); 1 for a leaf          */
     int level;       /* recursion depth of the node that issues it            */
     int flags;       /* bit q: product q (m == n) forms only its lower triangle;
-                        a mirror step fills the strict upper one              */
+                        a mirror step fills the strict upper one.  Bit 2: the
+                        executor does the next step (a mirror of this result,
+                        or its transpose into a block no operand occupies) in
+                        this product's epilogue, with the same result          */
     /* products: D = alpha * op_a * op_b + beta * C0 (+ I if add_identity)    */
     int64_t m[2], n[2], k[2];
     int a_buf[2], b_buf[2], c_buf[2], d_buf[2];  /* 0 = A, 1 = Ainv, 2 = workspace */

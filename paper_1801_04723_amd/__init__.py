@@ -214,7 +214,8 @@ def plan_describe(n: int, leaf: int, lda: int | None = None, ldx: int | None = N
                                   c=(o.c_buf[q], o.c_off[q], o.c_ld[q]),
                                   d=(o.d_buf[q], o.d_off[q], o.d_ld[q]),
                                   alpha=o.alpha[q], beta=o.beta[q], lower=bool(o.flags >> q & 1)))
-            ops.append(dict(kind="products", level=o.level, products=prods))
+            ops.append(dict(kind="products", level=o.level, products=prods,
+                            folds_next=bool(o.flags & 4)))
         elif o.kind == 4:
             ops.append(dict(kind="lu_leaf", level=o.level, L=o.leaf_order, col0=o.col0,
                             src=(o.a_buf[0], o.a_off[0], o.a_ld[0]),

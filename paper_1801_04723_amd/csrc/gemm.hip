@@ -61,6 +61,7 @@ struct GroupArgs {
     int32_t tile_start[N + 1];
     int32_t tiles_m[N];
 };
+static_assert(sizeof(GroupArgs<kMaxBatch>) <= 4096, "kernel arguments above 4 KiB");
 
 // Problem of workgroup `bid` (uniform scan over the prefix sums).
 template <int N>
@@ -213,9 +214,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
     // ---- epilogue: D = alpha * acc + beta * C0 (+ I) ------------------------
     const T *__restrict__ C0 = static_cast<const T *>(P.C0);
     T *D = static_cast<T *>(P.D);
+    T *DT = static_cast<T *>(P.DT);
     const double alpha = P.alpha, beta = P.beta;
     const bool use_c = (beta != 0.0) && (C0 != nullptr);
     const bool add_i = P.add_identity != 0;
+    const bool low = P.lower != 0;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int gm = m0 + wm0 + i * 16 + kcol;
@@ -224,11 +227,12 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gn = n0 + wn0 + j * 16 + Mma<T>::ncol(lane, v);
-                if (gm < M && gn < N) {
+                if (gm < M && gn < N && !(low && gm < gn)) {
                     double val = alpha * (double)acc[i][j][v];
                     if (use_c) val += beta * (double)C0[gm + (int64_t)gn * P.ldc];
                     if (add_i && gm == gn) val += 1.0;
                     D[gm + (int64_t)gn * P.ldd] = (T)val;
+                    if (DT != nullptr && !(low && gm == gn)) DT[gn + (int64_t)gm * P.lddt] = (T)val;
                 }
             }
         }
@@ -372,9 +376,11 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
 
     const T *__restrict__ C0 = static_cast<const T *>(P.C0);
     T *D = static_cast<T *>(P.D);
+    T *DT = static_cast<T *>(P.DT);
     const double alpha = P.alpha, beta = P.beta;
     const bool use_c = (beta != 0.0) && (C0 != nullptr);
     const bool add_i = P.add_identity != 0;
+    const bool low = P.lower != 0;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int gm = m0 + wm0 + i * 16 + c16;
@@ -383,11 +389,12 @@ __global__ void __launch_bounds__(256, 2) gemm_fast(GroupArgs<NG> g) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gn = n0 + wn0 + j * 16 + Mma<T>::ncol(lane, v);
-                if (gm < M && gn < N) {
+                if (gm < M && gn < N && !(low && gm < gn)) {
                     double val = alpha * (double)acc[i][j][v];
                     if (use_c) val += beta * (double)C0[gm + (int64_t)gn * P.ldc];
                     if (add_i && gm == gn) val += 1.0;
                     D[gm + (int64_t)gn * P.ldd] = (T)val;
+                    if (DT != nullptr && !(low && gm == gn)) DT[gn + (int64_t)gm * P.lddt] = (T)val;
                 }
             }
         }
@@ -581,9 +588,11 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
 
     const float *__restrict__ C0 = static_cast<const float *>(P.C0);
     float *D = static_cast<float *>(P.D);
+    float *DT = static_cast<float *>(P.DT);
     const double alpha = P.alpha, beta = P.beta;
     const bool use_c = (beta != 0.0) && (C0 != nullptr);
     const bool add_i = P.add_identity != 0;
+    const bool low = P.lower != 0;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int gm = m0 + wm0 + i * 16 + c16;
@@ -592,11 +601,12 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gn = n0 + wn0 + j * 16 + 4 * g4 + v;
-                if (gm < M && gn < N) {
+                if (gm < M && gn < N && !(low && gm < gn)) {
                     double val = alpha * (double)acc[i][j][v];
                     if (use_c) val += beta * (double)C0[gm + (int64_t)gn * P.ldc];
                     if (add_i && gm == gn) val += 1.0;
                     D[gm + (int64_t)gn * P.ldd] = (float)val;
+                    if (DT != nullptr && !(low && gm == gn)) DT[gn + (int64_t)gm * P.lddt] = (float)val;
                 }
             }
         }
@@ -748,6 +758,12 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
     bool done[kMaxBatch];
     int n_live = 0;
     double flops = 0, bytes = 0;
+    // the mirror form (DT == D) relies on the lower-triangle mode, which every
+    // tile shape honours for a square problem
+    for (int q = 0; q < count; ++q)
+        if (probs[q].DT != nullptr && probs[q].DT == probs[q].D &&
+            !(probs[q].lower && probs[q].m == probs[q].n))
+            return hipErrorInvalidValue;
     for (int q = 0; q < count; ++q) {
         if (probs[q].m <= 0 || probs[q].n <= 0) continue;
         part[n_live] = probs[q];
@@ -759,6 +775,7 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
         flops += (probs[q].lower && probs[q].m == probs[q].n) ? k * m * (m + cfgs[n_live - 1].tile)
                                                                : 2.0 * m * n * k;
         bytes += es * (m * k + k * n + m * n + ((probs[q].beta != 0.0) ? m * n : 0.0));
+        if (probs[q].DT != nullptr) bytes += es * m * n * (probs[q].lower ? 0.5 : 1.0);
     }
     const char *name = "gemm_empty";
     hipError_t e = hipSuccess;

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -312,6 +313,74 @@ GemmProb make_prob(char *const base[3], size_t es, const PGemm &g) {
 }
 
 namespace {
+// A rows x cols view; two views overlap only if they share a buffer and their
+// element ranges meet and, for equal leading dimensions with neither view
+// wrapping past a column end, both their row and their column ranges meet.
+bool views_disjoint(const Ref &x, int64_t xr, int64_t xc, const Ref &y, int64_t yr, int64_t yc) {
+    if (x.buf != y.buf || xr <= 0 || xc <= 0 || yr <= 0 || yc <= 0) return true;
+    const int64_t xe = x.off + (xc - 1) * x.ld + xr, ye = y.off + (yc - 1) * y.ld + yr;
+    if (xe <= y.off || ye <= x.off) return true;
+    if (x.ld == y.ld && x.ld > 0) {
+        const int64_t ld = x.ld;
+        const int64_t x0 = x.off % ld, x1 = x.off / ld, y0 = y.off % ld, y1 = y.off / ld;
+        if (x0 + xr > ld || y0 + yr > ld) return false;
+        return x0 + xr <= y0 || y0 + yr <= x0 || x1 + xc <= y1 || y1 + yc <= x1;
+    }
+    return false;
+}
+
+bool same_ref(const Ref &x, const Ref &y) { return x.buf == y.buf && x.off == y.off && x.ld == y.ld; }
+}  // namespace
+
+int fold_kind(const Plan &P, size_t i) {
+    if (i + 1 >= P.ops.size()) return 0;
+    const POp &op = P.ops[i], &nx = P.ops[i + 1];
+    if (op.kind != 0 || op.count != 1) return 0;
+    const PGemm &g = op.g[0];
+    if (g.m <= 0 || g.n <= 0) return 0;
+    const bool use_c = g.beta != 0.0;
+    if (nx.kind == 3) {
+        // mirror of this lower-half product's result; the in-place form
+        // C0 == D is safe because upper elements are neither read nor formed
+        if (!g.lower || g.m != g.n || !same_ref(nx.out, g.d) || nx.tm != g.m) return 0;
+        if (g.d.ld > INT32_MAX) return 0;
+        if (!views_disjoint(g.a, g.m, g.k, g.d, g.m, g.n) || !views_disjoint(g.b, g.k, g.n, g.d, g.m, g.n))
+            return 0;
+        if (use_c && !same_ref(g.c, g.d) && !views_disjoint(g.c, g.m, g.n, g.d, g.m, g.n)) return 0;
+        return 3;
+    }
+    if (nx.kind == 2) {
+        // transpose of this product's full result into a block of its own
+        if (g.lower || !same_ref(nx.in, g.d) || nx.tm != g.m || nx.tn != g.n) return 0;
+        if (nx.out.ld > INT32_MAX) return 0;
+        const Ref &t = nx.out;
+        if (!views_disjoint(t, g.n, g.m, g.a, g.m, g.k) || !views_disjoint(t, g.n, g.m, g.b, g.k, g.n) ||
+            !views_disjoint(t, g.n, g.m, g.d, g.m, g.n))
+            return 0;
+        if (use_c && !views_disjoint(t, g.n, g.m, g.c, g.m, g.n)) return 0;
+        return 2;
+    }
+    return 0;
+}
+
+bool fold_next_step(const Plan &P, size_t i, char *const base[3], size_t es, GemmProb pr[2]) {
+    if (es != 8) return false;  // the mirror and transpose steps are FP64 only
+    const int f = fold_kind(P, i);
+    if (f == 3) {
+        pr[0].DT = pr[0].D;
+        pr[0].lddt = (int32_t)P.ops[i].g[0].d.ld;
+        return true;
+    }
+    if (f == 2) {
+        const Ref &t = P.ops[i + 1].out;
+        pr[0].DT = base[t.buf] + (size_t)t.off * es;
+        pr[0].lddt = (int32_t)t.ld;
+        return true;
+    }
+    return false;
+}
+
+namespace {
 
 // ------------------------------------------------------------- tracing ----
 struct TraceRec {
@@ -410,12 +479,14 @@ inline void *at(const Exec &E, const Ref &r) {
 }
 
 hipError_t run_plan(const Plan &P, const Exec &E) {
-    for (const POp &op : P.ops) {
+    for (size_t i = 0; i < P.ops.size(); ++i) {
+        const POp &op = P.ops[i];
         TraceCtx ctx{E.s, op.level, nullptr};
         const bool tr = g_trace_on;
         if (op.kind == 0) {
             GemmProb pr[2];
             for (int q = 0; q < op.count; ++q) pr[q] = make_prob(E.base, E.es, op.g[q]);
+            if (fold_next_step(P, i, E.base, E.es, pr)) ++i;  // mirror / transpose in the epilogue
             LaunchInfo li{};
             if (tr) trace_cb(&ctx, li, 0);
             hipError_t e = gemm_launch(pr, op.count, E.gdt, E.s, &li);
@@ -867,6 +938,7 @@ int64_t describe_plan(const Plan &P, spin_plan_op *ops, int64_t cap, double *flo
                 o.beta[q] = g.beta;
                 if (g.lower) o.flags |= 1 << q;
             }
+            if (fold_kind(P, (size_t)i)) o.flags |= 4;
         } else if (op.kind == 4) {
             o.a_buf[0] = op.in.buf;
             o.a_off[0] = op.in.off;

@@ -22,7 +22,14 @@ constexpr int kLeafMaxOrder = 2048;
 
 // One block product  D = alpha * A * B + beta * C0 (+ I),  column-major views.
 // lower != 0 with m == n: only the tiles on or below the diagonal are
-// computed (a symmetric result whose strict upper part a mirror step fills).
+// computed and only the elements on or below the diagonal are stored (a
+// symmetric result whose strict upper part a mirror fills).
+// DT != nullptr: every stored element (i, j) is also stored at DT[j + i lddt]
+// (the result transposed, n x m); for a lower problem only the elements below
+// the diagonal are, so DT == D, lddt == ldd is the mirror.  DT must not
+// overlap A, B or C0 (except where DT == D == C0 in the mirror form).
+// 112 bytes: a group of kMaxBatch products stays within the 4 KiB of kernel
+// arguments.
 struct GemmProb {
     const void *A;
     const void *B;
@@ -33,7 +40,10 @@ struct GemmProb {
     int32_t add_identity;
     double alpha, beta;
     int32_t lower;
+    int32_t lddt;
+    void *DT;
 };
+static_assert(sizeof(GemmProb) == 112, "GemmProb layout");
 
 // One gemm_launch() call takes up to kMaxBatch independent products; products
 // that share a kernel configuration run in one grid (every workgroup finds

@@ -85,6 +85,16 @@ Layout layout_for(int64_t n, int64_t leaf, int mode, int64_t ws_elems, int64_t m
 // workspace at base[0..2] with element size es.
 GemmProb make_prob(char *const base[3], size_t es, const PGemm &g);
 
+// Whether the step after product step ops[i] can be done by that product's
+// epilogue with the same result bit for bit: 3 for the mirror of a lower-half
+// product's result, 2 for the transpose of a product's result into a block
+// that none of its operands occupies (single-product steps), else 0.
+int fold_kind(const Plan &P, size_t i);
+// Applies fold_kind to the kernel-level product pr[0] of an FP64 plan (element
+// size es == 8): sets pr[0].DT / lddt and returns true when ops[i + 1] is
+// taken over.
+bool fold_next_step(const Plan &P, size_t i, char *const base[3], size_t es, GemmProb pr[2]);
+
 // Order of the leading block when an order-m block is split.
 int64_t split_order(int64_t m);
 // Depth-first S-form schedule of Alg. 1 for an order-n matrix.

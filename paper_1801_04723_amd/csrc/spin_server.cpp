@@ -129,10 +129,12 @@ Step aux_step(int op) {
 }
 
 // gdt: product flavour of the plan's products; leaves use its storage type.
-// Transposes and mirrors (FP64 plans only) become auxiliary steps.
+// Transposes and mirrors (FP64 plans only) that no product epilogue takes
+// over become auxiliary steps.
 void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, int *status,
                     void *leaf_scratch, std::vector<Step> &out) {
-    for (const POp &op : P.ops) {
+    for (size_t i = 0; i < P.ops.size(); ++i) {
+        const POp &op = P.ops[i];
         Step st;
         std::memset(&st, 0, sizeof(st));
         st.dt = op.kind == 0 ? gdt : storage_type(gdt);
@@ -140,6 +142,9 @@ void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, in
             st.kind = STEP_GEMM;
             st.nprob = op.count;
             for (int q = 0; q < op.count; ++q) st.prob[q] = make_prob(base, es, op.g[q]);
+            // as in the single-call executor: a following mirror or transpose
+            // is done by this product's epilogue
+            if (fold_next_step(P, i, base, es, st.prob)) ++i;
         } else if (op.kind == 2 || op.kind == 3) {
             st.kind = STEP_AUX;
             st.aux = op.kind == 2 ? AUX_TRANSPOSE : AUX_MIRROR;

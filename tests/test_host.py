@@ -138,8 +138,14 @@ def test_split_rule_matches_oracle(m):
     assert n1 == oracle.split(m)
 
 
-def _run_schedule_on_cpu(A, leaf, spd=False, lu=False):
-    """Replay the library's schedule with the oracle's GEMM and leaf routines."""
+def _run_schedule_on_cpu(A, leaf, spd=False, lu=False, fold=False):
+    """Replay the library's schedule with the oracle's GEMM and leaf routines.
+
+    fold=True replays it as the executor runs it: a product flagged
+    folds_next stores only its lower triangle when it is a lower-half product,
+    and also stores its result transposed (onto its own upper triangle for a
+    mirror, into the transpose's destination otherwise); the next step is
+    skipped."""
     n = A.shape[0]
     ops, _ = S.plan_describe(n, leaf, spd=spd, lu=lu)
     ws = S.plan_ws_elems_lu(n, leaf) if lu else S.plan_ws_elems(n, leaf)
@@ -151,7 +157,11 @@ def _run_schedule_on_cpu(A, leaf, spd=False, lu=False):
         flat = bufs[b]
         return np.lib.stride_tricks.as_strided(flat[off:], shape=(r, c), strides=(8, 8 * ld))
 
-    for o in ops:
+    skip = False
+    for i, o in enumerate(ops):
+        if skip:
+            skip = False
+            continue
         if o["kind"] == "leaf":
             L = o["L"]
             src = np.array(view(o["src"], L, L))
@@ -186,6 +196,22 @@ def _run_schedule_on_cpu(A, leaf, spd=False, lu=False):
                 if p["beta"] != 0.0:
                     d = d + p["beta"] * np.array(view(p["c"], p["m"], p["n"]))
                 results.append((p, d))
+            if fold and o["folds_next"]:
+                (p, d), = results
+                nxt = ops[i + 1]
+                dv = view(p["d"], p["m"], p["n"])
+                if p["lower"]:
+                    assert nxt["kind"] == "mirror" and nxt["dst"] == p["d"]
+                    il = np.tril_indices(p["m"])
+                    dv[il] = d[il]
+                    iu = np.triu_indices(p["m"], 1)
+                    dv[iu] = d.T[iu]
+                else:
+                    assert nxt["kind"] == "transpose" and nxt["src"] == p["d"]
+                    dv[...] = d
+                    view(nxt["dst"], p["n"], p["m"])[...] = d.T
+                skip = True
+                continue
             for p, d in results:
                 view(p["d"], p["m"], p["n"])[...] = d
     return bufs[1].reshape((n, n), order="F")
@@ -207,6 +233,27 @@ def test_spd_schedule_replay_equals_oracle_bitwise(n, leaf):
     product and leaf routines, is O3 bit for bit (S-form against V-form)."""
     A = W.spd_gram(n, 2)
     X = _run_schedule_on_cpu(A, leaf, spd=True)
+    ref, info = oracle.strassen_inv_spd(A, leaf)
+    assert info == 0
+    assert np.array_equal(X, ref)
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 64), (200, 32), (300, 64), (130, 64), (5, 2)])
+def test_spd_folded_schedule_replay_equals_oracle_bitwise(n, leaf):
+    """Every mirror and transpose of the symmetric schedule is folded into the
+    epilogue of the product before it, and the schedule run that way is still
+    O3 bit for bit."""
+    A = W.spd_gram(n, 2)
+    ops, _ = S.plan_describe(n, leaf, spd=True)
+    for i, o in enumerate(ops):
+        if o["kind"] in ("mirror", "transpose"):
+            assert ops[i - 1]["kind"] == "products" and ops[i - 1]["folds_next"]
+    for lda, ldx in ((n, n), (n + 3, n + 5)):
+        assert all(ops[i - 1]["folds_next"]
+                   for ops in [S.plan_describe(n, leaf, lda, ldx, spd=True)[0]]
+                   for i, o in enumerate(ops) if o["kind"] in ("mirror", "transpose"))
+    assert not any(o.get("folds_next") for o in S.plan_describe(n, leaf)[0])
+    X = _run_schedule_on_cpu(A, leaf, spd=True, fold=True)
     ref, info = oracle.strassen_inv_spd(A, leaf)
     assert info == 0
     assert np.array_equal(X, ref)
