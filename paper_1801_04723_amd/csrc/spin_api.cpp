@@ -13,8 +13,10 @@
 //   locInverse (Alg. 2, leaf case) -> the leaf Gauss-Jordan kernels.
 // Every internal node issues four launches: {II, III} grouped, S, {C12, C21}
 // grouped, and C11 = C11 - III C21 in place.  The schedule for symmetric
-// matrices (spin_invert_spd) issues five: II, S, C21, the transpose
-// C12 = C21^T, and C11 = C11 - C12 II.
+// matrices (spin_invert_spd) lists II, S with its mirror, C21, the transpose
+// C12 = C21^T, and C11 = C11 - C12 II with its mirror; the executor folds the
+// mirrors and the transpose into the product epilogues, so it too launches
+// four kernels per node.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

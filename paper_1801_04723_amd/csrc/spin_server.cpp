@@ -7,8 +7,8 @@
 // every active request: block products from all requests go into grouped
 // matrix-core launches (one grid per kernel configuration), whole leaves into
 // one batched leaf launch, and the small auxiliary kernels (status resets,
-// conversions, norms, and the symmetric schedule's transposes and mirrors)
-// run as they come.
+// conversions, norms, and any transpose or mirror of the symmetric schedule
+// that no product epilogue takes over) run as they come.
 // Steps of one request stay in order (one product/leaf step per request per
 // tick, all launched on one stream), and every kernel computes each
 // product/leaf exactly as it does alone, so a request's result is bit for bit
