@@ -135,7 +135,7 @@ def serving(rate: float, seconds: float, symmetric: bool = True):
     st = serve.run_trace(trace, leaf=128, ns_steps=2, split_n=[512, 2048], symmetric=symmetric)
     st["workload"] = (f"Poisson {rate:g} req/s for {seconds:g} s, n log-uniform 64..4096 (x64), "
                       "50% diag-dominant / 50% SPD, 70% mixed FP32+2 Newton / 30% FP64 "
-                      f"({'SPD ones on the symmetric schedule' if symmetric else 'plain schedule'}), leaf 128; "
+                      f"({'SPD FP64 requests on the symmetric schedule' if symmetric else 'plain schedule'}), leaf 128; "
                       "three server lanes on three streams (n < 512, 512 <= n < 2048, n >= 2048)")
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
 

@@ -85,10 +85,13 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
                               hi*hi + lo*hi + hi*lo accumulated in FP32
                               (about 16 significant bits per operand); needs
                               one refinement step more than SPIN_MIXED_FP32   */
-/* Schedule flag for the batched and serving entry points only: a request of
- * mode SPIN_FP64 | SPIN_SYMMETRIC runs the symmetric schedule of
- * spin_invert_spd (A must be exactly symmetric) and its result is bit for bit
- * spin_invert_spd's.  Any other combination with this flag is SPIN_E_MODE. */
+/* Schedule flag, OR-ed into a mode (A must then be exactly symmetric): the
+ * recursion runs the symmetric schedule of spin_invert_spd.  Accepted by
+ * spin_invert_mixed (mixed modes: the FP32-storage recursion with the mode's
+ * product flavour, then the same FP64 refinement) and by the batched and
+ * serving entry points (SPIN_FP64 | SPIN_SYMMETRIC gives spin_invert_spd's
+ * result bit for bit, a mixed mode spin_invert_mixed's with the flag).
+ * Anywhere else, or with an unknown mode, it is SPIN_E_MODE. */
 #define SPIN_SYMMETRIC 16
 
 /* ---- FP64 inversion ------------------------------------------------------- */
@@ -147,7 +150,9 @@ typedef struct spin_report {
  * leaves, followed by `ns_steps` (0..8) FP64 Newton steps
  *     R = I - A X,  X <- X + X R
  * (Newton iteration as the stabiliser of Strassen inversion, Sec. 2.1).
- * If `rep` is non-NULL the call waits for the stream, evaluates both residuals
+ * mode | SPIN_SYMMETRIC (exactly symmetric A) runs the recursion on the
+ * symmetric schedule of spin_invert_spd, about half the block-product work;
+ * the refinement is unchanged.  If `rep` is non-NULL the call waits for the stream, evaluates both residuals
  * on the GPU and fills *rep; with rep == NULL the call is asynchronous and
  * no residual is computed. */
 int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
@@ -192,8 +197,8 @@ void spin_release(void);
 
 /* ---- batched inversion and continuous batching ---------------------------- */
 /* Inverts `count` independent matrices (each column-major, its own order n[i]
- * and leading dimensions; mode[i] = SPIN_FP64, SPIN_FP64 | SPIN_SYMMETRIC or
- * one of the mixed modes with `ns_steps` refinement steps) with cross-request
+ * and leading dimensions; mode[i] = SPIN_FP64 or one of the mixed modes with
+ * `ns_steps` refinement steps, either optionally | SPIN_SYMMETRIC) with cross-request
  * batching: at each step the block products of all requests run in grouped
  * matrix-core launches and their leaves in one batched leaf launch.  Every
  * request's result is bit for bit the one spin_invert / spin_invert_spd /

@@ -27,13 +27,15 @@ FP64 = 0
 MIXED_FP32 = 1
 MIXED_BF16 = 2
 MIXED_BF16X3 = 3
-# Flag for invert_batch / Server / server_request_bytes: FP64 | SYMMETRIC runs
-# the symmetric schedule of invert_spd (exactly symmetric inputs only).
+# Flag OR-ed into a mode for invert_mixed, invert_batch, Server and
+# server_request_bytes: the recursion runs the symmetric schedule of invert_spd
+# (exactly symmetric inputs only).
 SYMMETRIC = 16
 MODES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32,
          "bf16": MIXED_BF16, "mixed_bf16": MIXED_BF16,
          "bf16x3": MIXED_BF16X3, "mixed_bf16x3": MIXED_BF16X3,
-         "fp64_sym": FP64 | SYMMETRIC}
+         "fp64_sym": FP64 | SYMMETRIC, "fp32_sym": MIXED_FP32 | SYMMETRIC,
+         "bf16_sym": MIXED_BF16 | SYMMETRIC, "bf16x3_sym": MIXED_BF16X3 | SYMMETRIC}
 NS_DIVERGED = -100
 MAX_LEAF = 2048
 

@@ -366,7 +366,7 @@ int fold_kind(const Plan &P, size_t i) {
 }
 
 bool fold_next_step(const Plan &P, size_t i, char *const base[3], size_t es, GemmProb pr[2]) {
-    if (es != 8) return false;  // the mirror and transpose steps are FP64 only
+    if (es != 8 && es != 4) return false;
     const int f = fold_kind(P, i);
     if (f == 3) {
         pr[0].DT = pr[0].D;
@@ -695,11 +695,14 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
                       spin_stream_t stream) {
     int rc = validate(A, n, lda, Ainv, ldx, leaf);
     if (rc) return rc;
-    if (!is_mixed_mode(mode) || ns_steps < 0 || ns_steps > kNormSlots) return SPIN_E_MODE;
+    // SPIN_SYMMETRIC: the symmetric schedule with the mode's product flavour
+    const bool sym = (mode & SPIN_SYMMETRIC) != 0;
+    const int pmode = mode & ~SPIN_SYMMETRIC;
+    if (!is_mixed_mode(pmode) || ns_steps < 0 || ns_steps > kNormSlots) return SPIN_E_MODE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(g_mu);
-    Plan P = make_plan(n, n, n, leaf);
-    Layout L = layout_for(n, leaf, mode, P.ws_elems, P.max_leaf);
+    Plan P = sym ? make_plan_spd(n, n, n, leaf) : make_plan(n, n, n, leaf);
+    Layout L = layout_for(n, leaf, pmode, P.ws_elems, P.max_leaf);
     Workspace *w = nullptr;
     rc = ws_acquire(s, L.total, &w);
     if (rc) return rc;
@@ -723,7 +726,7 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
         e = cast_f64_to_f32(A, lda, A32, n, n, n, qs);
         if (e != hipSuccess) return e;
         Exec E{qs, {(char *)A32, (char *)X32, base + L.rec_off}, 4, kF32, status,
-               base + L.leaf_off, mixed_product_type(mode)};
+               base + L.leaf_off, mixed_product_type(pmode)};
         e = run_plan(P, E);
         if (e != hipSuccess) return e;
         e = cast_f32_to_f64(X32, n, buf0, ld0, n, n, qs);

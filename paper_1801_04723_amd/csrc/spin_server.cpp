@@ -84,9 +84,13 @@ class PoolAllocator {
 enum StepKind { STEP_GEMM = 0, STEP_LEAF = 1, STEP_AUX = 2 };
 enum AuxOp { AUX_RESET, AUX_CAST_IN, AUX_WIDEN, AUX_FROB, AUX_NSCHECK, AUX_TRANSPOSE, AUX_MIRROR };
 
-// FP64 request on the symmetric schedule of spin_invert_spd.
+// A mode with SPIN_SYMMETRIC runs the symmetric schedule of spin_invert_spd
+// with the mode's product flavour.
 constexpr int kModeSym = SPIN_FP64 | SPIN_SYMMETRIC;
-bool server_mode(int mode) { return is_mode(mode) || mode == kModeSym; }
+bool server_mode(int mode) {
+    return is_mode(mode) || ((mode & SPIN_SYMMETRIC) && is_mode(mode & ~SPIN_SYMMETRIC));
+}
+int product_mode(int mode) { return mode & ~SPIN_SYMMETRIC; }
 
 struct Step {
     int kind;
@@ -129,9 +133,9 @@ Step aux_step(int op) {
 }
 
 // gdt: product flavour of the plan's products; leaves use its storage type.
-// Transposes and mirrors (FP64 plans only) that no product epilogue takes
-// over become auxiliary steps.
-void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, int *status,
+// Transposes and mirrors that no product epilogue takes over become auxiliary
+// steps (FP64 kernels); in an FP32-storage plan that is an error (false).
+bool add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, int *status,
                     void *leaf_scratch, std::vector<Step> &out) {
     for (size_t i = 0; i < P.ops.size(); ++i) {
         const POp &op = P.ops[i];
@@ -146,6 +150,7 @@ void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, in
             // is done by this product's epilogue
             if (fold_next_step(P, i, base, es, st.prob)) ++i;
         } else if (op.kind == 2 || op.kind == 3) {
+            if (es != 8) return false;
             st.kind = STEP_AUX;
             st.aux = op.kind == 2 ? AUX_TRANSPOSE : AUX_MIRROR;
             if (op.kind == 2) {
@@ -165,11 +170,12 @@ void add_plan_steps(const Plan &P, char *const base[3], size_t es, DType gdt, in
         }
         out.push_back(st);
     }
+    return true;
 }
 
 // The steps of one request: the same launches spin_invert / spin_invert_spd /
 // spin_invert_mixed make, in the same order, with the request's own workspace.
-void build_steps(Request &r, int64_t leaf, int ns_steps) {
+bool build_steps(Request &r, int64_t leaf, int ns_steps) {
     const int64_t n = r.n;
     char *w = r.ws;
     int *status = reinterpret_cast<int *>(w);
@@ -183,11 +189,11 @@ void build_steps(Request &r, int64_t leaf, int ns_steps) {
                                     : make_plan(n, r.lda, r.ldx, leaf);
         Layout L = layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf);
         char *const base[3] = {(char *)r.A, (char *)r.X, w + L.rec_off};
-        add_plan_steps(P, base, 8, kF64, status, w + L.leaf_off, r.steps);
-        return;
+        return add_plan_steps(P, base, 8, kF64, status, w + L.leaf_off, r.steps);
     }
-    Plan P = make_plan(n, n, n, leaf);
-    Layout L = layout_for(n, leaf, r.mode, P.ws_elems, P.max_leaf);
+    const int pm = product_mode(r.mode);
+    Plan P = (r.mode & SPIN_SYMMETRIC) ? make_plan_spd(n, n, n, leaf) : make_plan(n, n, n, leaf);
+    Layout L = layout_for(n, leaf, pm, P.ws_elems, P.max_leaf);
     float *A32 = reinterpret_cast<float *>(w + L.a32_off);
     float *X32 = reinterpret_cast<float *>(w + L.x32_off);
     double *R = reinterpret_cast<double *>(w + L.r_off);
@@ -200,7 +206,8 @@ void build_steps(Request &r, int64_t leaf, int ns_steps) {
     c.src = r.A, c.lds = r.lda, c.dst = A32, c.ldd = n, c.m = n, c.n = n;
     r.steps.push_back(c);
     char *const base[3] = {(char *)A32, (char *)X32, w + L.rec_off};
-    add_plan_steps(P, base, 4, mixed_product_type(r.mode), status, w + L.leaf_off, r.steps);
+    if (!add_plan_steps(P, base, 4, mixed_product_type(pm), status, w + L.leaf_off, r.steps))
+        return false;
     Step wd = aux_step(AUX_WIDEN);
     wd.src = X32, wd.lds = n, wd.dst = buf0, wd.ldd = ld0, wd.m = n, wd.n = n;
     r.steps.push_back(wd);
@@ -232,6 +239,7 @@ void build_steps(Request &r, int64_t leaf, int ns_steps) {
                              0, 1.0, 1.0};
         r.steps.push_back(u);
     }
+    return true;
 }
 
 hipError_t run_aux(const Step &s, hipStream_t st) {
@@ -279,12 +287,8 @@ struct spin_server {
 namespace {
 
 size_t request_bytes(int64_t n, int64_t leaf, int mode) {
-    if (mode == kModeSym) {
-        Plan P = make_plan_spd(n, n, n, leaf);
-        return layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf).total;
-    }
-    Plan P = make_plan(n, n, n, leaf);
-    return layout_for(n, leaf, mode, P.ws_elems, P.max_leaf).total;
+    Plan P = (mode & SPIN_SYMMETRIC) ? make_plan_spd(n, n, n, leaf) : make_plan(n, n, n, leaf);
+    return layout_for(n, leaf, product_mode(mode), P.ws_elems, P.max_leaf).total;
 }
 
 int hipfail(hipError_t e) {
@@ -380,7 +384,7 @@ int spin_server_tick(spin_server *s, spin_stream_t stream) {
     hipError_t e = hipSuccess;
     for (Request *r : s->active) {
         if (r->done) continue;  // all steps launched, waiting for completion
-        if (r->steps.empty()) build_steps(*r, s->leaf, s->ns_steps);
+        if (r->steps.empty() && !build_steps(*r, s->leaf, s->ns_steps)) return SPIN_E_MODE;
         // leading auxiliary steps run now; then one product/leaf step joins the groups
         while (r->next < r->steps.size() && e == hipSuccess) {
             const Step &stp = r->steps[r->next];

@@ -72,7 +72,10 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
     taking turns in one stream; each request's result is the same either way.
 
     symmetric: FP64 requests for SPD matrices (exactly symmetric inputs) run
-    the symmetric schedule (mode FP64 | SYMMETRIC), about half the flops."""
+    the symmetric schedule (mode FP64 | SYMMETRIC), about half the flops.
+    Mixed requests keep the plain schedule: their FP64 refinement dominates,
+    so the symmetric one saves only a few percent there and leaves a larger
+    residual after the same number of Newton steps."""
     import torch
     pool = pool or MatrixPool()
     # materialise the inputs before the clock starts

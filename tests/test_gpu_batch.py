@@ -39,7 +39,8 @@ def _solo(S, a, mode, leaf, ns_steps):
 REQS = [(256, "dd", "fp64"), (320, "spd", "fp32"), (64, "dd", "fp64"), (512, "spdk", "fp32"),
         (130, "dd", "fp64"), (1024, "spd", "fp64"), (192, "spdk", "fp32"), (40, "dd", "fp32"),
         (384, "dd", "bf16x3"), (200, "dd", "bf16"), (512, "spd", "fp64_sym"),
-        (200, "spdk", "fp64_sym"), (64, "spd", "fp64_sym")]
+        (200, "spdk", "fp64_sym"), (64, "spd", "fp64_sym"), (320, "spdk", "fp32_sym"),
+        (256, "spd", "bf16x3_sym")]
 
 
 def _mat(n, kind, seed):

@@ -130,6 +130,34 @@ def test_mixed_bf16x3_spd_refined_to_fp64(torch_cuda, n, leaf):
     assert np.linalg.norm(X - ref) / np.linalg.norm(ref) <= max(1e-13, 100 * kap * U)
 
 
+@pytest.mark.parametrize("mode,steps", [("fp32", 2), ("bf16x3", 3)])
+@pytest.mark.parametrize("n,leaf", [(512, 128), (1000, 64)])
+def test_mixed_symmetric_schedule_refined_to_fp64(torch_cuda, mode, steps, n, leaf):
+    """The symmetric schedule with FP32-storage products (mode | SYMMETRIC):
+    unrefined residual of the same order as the plain schedule's, refined to
+    the FP64 target.  Newton steps square the error of X0 until the FP64
+    floor of about kappa u, so after the same number of steps the distance to
+    O3 is compared with the plain schedule's (or that floor), not with the
+    floor alone: two steps from an FP32 start at kappa = 1e4 can still sit
+    above it."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    A = W.spd_spectrum(n, seed=n + 7, kappa=1e4)
+    dA = _dev64(torch, A)
+    Xs, rs = S.invert_mixed(dA, leaf=leaf, mode=mode + "_sym", ns_steps=steps, report=True)
+    Xp, rp = S.invert_mixed(dA, leaf=leaf, mode=mode, ns_steps=steps, report=True)
+    Xs = _host(Xs)
+    assert rs["status"] == 0 and rp["status"] == 0, (rs, rp)
+    assert rs["rho_before"] <= 10 * rp["rho_before"], (rs, rp)
+    assert rs["rho_after"] <= 1e-12, rs
+    assert oracle.residual(A, Xs) <= 1e-12
+    ref, _ = oracle.strassen_inv_spd(A, leaf)
+    kap = np.linalg.cond(A)
+    err_s = np.linalg.norm(Xs - ref) / np.linalg.norm(ref)
+    err_p = np.linalg.norm(_host(Xp) - ref) / np.linalg.norm(ref)
+    assert err_s <= max(10 * err_p, 100 * kap * U), (err_s, err_p)
+
+
 def test_mixed_bf16_diag_dominant_refined(torch_cuda):
     import paper_1801_04723_amd as S
     torch = torch_cuda

@@ -412,13 +412,13 @@ def test_server_slot_cap_and_validation():
 
 def test_server_symmetric_mode_validation():
     """FP64 | SYMMETRIC is a server/batch mode with the symmetric schedule's
-    footprint; the flag with a mixed mode is rejected everywhere."""
+    footprint; the flag with an unknown mode is rejected everywhere."""
     L = S.lib()
     leaf = 64
     for n in (1, 64, 200, 1024):
         sym = S.server_request_bytes(n, leaf, "fp64_sym")
         assert 0 < sym <= S.server_request_bytes(n, leaf, "fp64")
-    bad = S.MIXED_FP32 | S.SYMMETRIC
+    bad = 4 | S.SYMMETRIC
     assert S.server_request_bytes(256, leaf, bad) == 0
     assert S.server_request_bytes(256, leaf, S.SYMMETRIC | 32) == 0
     srv = S.Server(1 << 30, max_active=2, leaf=leaf)
@@ -433,3 +433,26 @@ def test_server_symmetric_mode_validation():
     rc = L.spin_invert_batch(1, ptrs(_fake(4)), i64(256), i64(256), ptrs(_fake(5)), i64(256),
                              (ctypes.c_int * 1)(bad), leaf, 2, None, None)
     assert rc == -6
+
+
+def test_symmetric_mixed_modes_validation():
+    """Mixed modes with SYMMETRIC: the symmetric schedule's footprint (no more
+    than the plain one's) in the server, accepted by spin_invert_mixed's
+    validation; FP64 | SYMMETRIC is not a mixed mode."""
+    L = S.lib()
+    leaf = 64
+    for m in (S.MIXED_FP32, S.MIXED_BF16, S.MIXED_BF16X3):
+        for n in (1, 200, 1024):
+            sym = S.server_request_bytes(n, leaf, m | S.SYMMETRIC)
+            assert 0 < sym <= S.server_request_bytes(n, leaf, m)
+    for name in ("fp32_sym", "bf16_sym", "bf16x3_sym"):
+        assert S.MODES[name] & S.SYMMETRIC
+    srv = S.Server(1 << 30, max_active=2, leaf=leaf)
+    assert L.spin_server_submit(srv._h, _fake(0), 256, 256, _fake(1), 256,
+                                S.MIXED_BF16X3 | S.SYMMETRIC, 0) == 0
+    assert L.spin_server_submit(srv._h, _fake(2), 256, 256, _fake(3), 256, 4 | S.SYMMETRIC, 1) == -6
+    srv.close()
+    p = ctypes.c_void_p
+    A, X = p(0x10000000), p(0x20000000)
+    assert L.spin_invert_mixed(A, 8, 8, X, 8, 4, S.FP64 | S.SYMMETRIC, 2, None, p(0)) == -6
+    assert L.spin_invert_mixed(A, 8, 8, X, 8, 4, S.MIXED_FP32 | S.SYMMETRIC, 9, None, p(0)) == -6
