@@ -365,6 +365,13 @@ int fold_kind(const Plan &P, size_t i) {
     return 0;
 }
 
+bool plan_folds_all(const Plan &P) {
+    for (size_t i = 0; i < P.ops.size(); ++i)
+        if ((P.ops[i].kind == 2 || P.ops[i].kind == 3) && (i == 0 || fold_kind(P, i - 1) == 0))
+            return false;
+    return true;
+}
+
 bool fold_next_step(const Plan &P, size_t i, char *const base[3], size_t es, GemmProb pr[2]) {
     if (es != 8 && es != 4) return false;
     const int f = fold_kind(P, i);
@@ -702,6 +709,8 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(g_mu);
     Plan P = sym ? make_plan_spd(n, n, n, leaf) : make_plan(n, n, n, leaf);
+    // FP32 storage has no mirror or transpose kernel of its own
+    if (!plan_folds_all(P)) return SPIN_E_MODE;
     Layout L = layout_for(n, leaf, pmode, P.ws_elems, P.max_leaf);
     Workspace *w = nullptr;
     rc = ws_acquire(s, L.total, &w);

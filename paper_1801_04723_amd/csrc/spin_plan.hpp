@@ -90,6 +90,9 @@ GemmProb make_prob(char *const base[3], size_t es, const PGemm &g);
 // product's result, 2 for the transpose of a product's result into a block
 // that none of its operands occupies (single-product steps), else 0.
 int fold_kind(const Plan &P, size_t i);
+// Whether every mirror and transpose of P is taken over by the product before
+// it (required for plans on FP32 storage).
+bool plan_folds_all(const Plan &P);
 // Applies fold_kind to the kernel-level product pr[0] of a plan with element
 // size es (8: FP64, 4: FP32 storage): sets pr[0].DT / lddt and returns true
 // when ops[i + 1] is taken over.

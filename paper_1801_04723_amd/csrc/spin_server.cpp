@@ -286,6 +286,12 @@ struct spin_server {
 
 namespace {
 
+// A symmetric request on FP32 storage needs every mirror and transpose folded.
+bool schedule_ok(int64_t n, int64_t leaf, int mode) {
+    if (!(mode & SPIN_SYMMETRIC) || product_mode(mode) == SPIN_FP64) return true;
+    return plan_folds_all(make_plan_spd(n, n, n, leaf));
+}
+
 size_t request_bytes(int64_t n, int64_t leaf, int mode) {
     Plan P = (mode & SPIN_SYMMETRIC) ? make_plan_spd(n, n, n, leaf) : make_plan(n, n, n, leaf);
     return layout_for(n, leaf, product_mode(mode), P.ws_elems, P.max_leaf).total;
@@ -342,7 +348,7 @@ int spin_server_submit(spin_server *s, const double *A, int64_t n, int64_t lda, 
     if (!s || !A || !Ainv) return SPIN_E_NULL;
     if (n < 1 || n > SPIN_MAX_N) return SPIN_E_N;
     if (lda < n || ldx < n) return SPIN_E_LD;
-    if (!server_mode(mode)) return SPIN_E_MODE;
+    if (!server_mode(mode) || !schedule_ok(n, s->leaf, mode)) return SPIN_E_MODE;
     const char *a0 = reinterpret_cast<const char *>(A), *x0 = reinterpret_cast<const char *>(Ainv);
     const char *a1 = a0 + ((size_t)(n - 1) * lda + n) * 8, *x1 = x0 + ((size_t)(n - 1) * ldx + n) * 8;
     if (a0 < x1 && x0 < a1) return SPIN_E_ALIAS;
@@ -384,7 +390,11 @@ int spin_server_tick(spin_server *s, spin_stream_t stream) {
     hipError_t e = hipSuccess;
     for (Request *r : s->active) {
         if (r->done) continue;  // all steps launched, waiting for completion
-        if (r->steps.empty() && !build_steps(*r, s->leaf, s->ns_steps)) return SPIN_E_MODE;
+        // submit checked that the request's schedule builds
+        if (r->steps.empty() && !build_steps(*r, s->leaf, s->ns_steps)) {
+            e = hipErrorInvalidValue;
+            break;
+        }
         // leading auxiliary steps run now; then one product/leaf step joins the groups
         while (r->next < r->steps.size() && e == hipSuccess) {
             const Step &stp = r->steps[r->next];
@@ -472,7 +482,7 @@ int spin_server_stats(spin_server *s, int64_t *queued, int64_t *active, size_t *
 
 size_t spin_server_request_bytes(int64_t n, int64_t leaf, int mode) {
     if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > SPIN_MAX_LEAF) return 0;
-    if (!server_mode(mode)) return 0;
+    if (!server_mode(mode) || !schedule_ok(n, leaf, mode)) return 0;
     return al256(request_bytes(n, leaf, mode));
 }
 
@@ -487,7 +497,7 @@ int spin_invert_batch(int64_t count, const double *const *A, const int64_t *n, c
     size_t total = 0;
     for (int64_t i = 0; i < count; ++i) {
         if (n[i] < 1 || n[i] > SPIN_MAX_N) return SPIN_E_N;
-        if (!server_mode(mode[i])) return SPIN_E_MODE;
+        if (!server_mode(mode[i]) || !schedule_ok(n[i], leaf, mode[i])) return SPIN_E_MODE;
         total += al256(request_bytes(n[i], leaf, mode[i]));
     }
     spin_server *s = spin_server_create(total, (int)count, leaf, ns_steps);
