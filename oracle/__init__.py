@@ -8,11 +8,13 @@ Contents
   * ``gj_inv``        -- O1, Gauss-Jordan with partial pivoting on [A | I]
                          (leaf inversion; the paper leaves the method open,
                          Alg. 1, Sec. 3.1).
-  * ``strassen_inv``  -- O2, Strassen's scheme exactly as Alg. 1 lists it
-                         (V-form: V = A21 A11^-1 A12 - A22, C22 = -V^-1).
-  * ``strassen_inv_spd`` -- O3, Alg. 1 specialised to symmetric A (the
-                         positive-definite matrices of Sec. 2.1): III = II^T,
-                         so IV = II A12, C12 = C21^T and VII = C12 II; V and
+  * ``strassen_inv``  -- O2, the block-inverse identity Alg. 1 (Sec. 3.1)
+                         evaluates, recursing on the leading block and on the
+                         negated Schur complement A21 A11^-1 A12 - A22.
+  * ``strassen_inv_spd`` -- O2 specialised to symmetric A (the positive-
+                         definite matrices of Sec. 2.1): the column factor
+                         A11^-1 A12 is the transpose of the row factor
+                         A21 A11^-1, so C12 = C21^T; the Schur complement and
                          C11 keep their lower triangles, mirrored.
   * ``lu_inv``        -- O4, inversion through a block LU factorisation
                          without pivoting: L^-1 and U^-1 by block recursion,
@@ -124,7 +126,7 @@ def gj_inv(a, lib: ctypes.CDLL | None = None):
 
 
 def strassen_inv(a, leaf: int, lib: ctypes.CDLL | None = None):
-    """O2 (Alg. 1, V-form): returns (X, info)."""
+    """O2 (block-inverse identity of Alg. 1): returns (X, info)."""
     lib = lib or load()
     a = _f64(a)
     n = a.shape[0]
@@ -135,7 +137,7 @@ def strassen_inv(a, leaf: int, lib: ctypes.CDLL | None = None):
 
 
 def strassen_inv_spd(a, leaf: int, lib: ctypes.CDLL | None = None):
-    """O3 (Alg. 1 for symmetric A, four products per node): returns (X, info)."""
+    """O3 (O2 for symmetric A, four products per split): returns (X, info)."""
     lib = lib or load()
     a = _f64(a)
     n = a.shape[0]

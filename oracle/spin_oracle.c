@@ -17,14 +17,11 @@
  *                        paper's `multiply` computes, Sec. 3.3).
  *   oracle_gj_inv        O1: Gauss-Jordan elimination on [A | I] with partial
  *                        pivoting (one concrete choice for the leaf inversion,
- *                        which the paper leaves open: Alg. 1, "invert A in any
- *                        approach").
- *   oracle_strassen_inv  O2: Strassen's inversion scheme, Alg. 1 (Sec. 3.1),
- *                        in its literal form: I = A11^-1, II = A21 I,
- *                        III = I A12, IV = A21 III, V = IV - A22, VI = V^-1,
- *                        C12 = III VI, C21 = VI II, VII = III C21,
- *                        C11 = I - VII, C22 = -VI; recursion stops at the
- *                        leaf threshold and inverts the leaf with O1.
+ *                        whose method the paper leaves open, Alg. 1).
+ *   oracle_strassen_inv  O2: the block-inverse identity of Alg. 1 (Sec. 3.1),
+ *                        recursing on the leading block and on the (negated)
+ *                        Schur complement until a block reaches the leaf
+ *                        threshold, whose inverse O1 computes.
  *   oracle_ns_step       one Newton(-Schulz) refinement step
  *                        X' = X + X (I - A X) (Sec. 2.1 cites Newton iteration
  *                        as the stabiliser of Strassen inversion).
@@ -176,51 +173,87 @@ static void mat_copy(const double *P, int64_t ldp, double *R, int64_t ldr, int64
             AT(R, i, j, ldr) = AT(P, i, j, ldp);
 }
 
-/* O2, Alg. 1.  C (m x m, ldc) = A^-1.  col0 is the global column offset of
- * this block, so that a failing leaf reports a global 1-based column. */
+/* Factors of one split of an order-m block into A11 (n1 x n1), A12, A21 and
+ * A22 (n2 x n2).  With P = A11^-1 and the Schur complement S = A22 - A21 P A12
+ * the inverse is
+ *
+ *     [ P + (P A12) S^-1 (A21 P)     -(P A12) S^-1 ]
+ *     [ -S^-1 (A21 P)                 S^-1         ]
+ *
+ * Alg. 1 carries N = -S instead (A21 (P A12) - A22) and its inverse T = N^-1,
+ * so that the off-diagonal blocks are (P A12) T and T (A21 P) with no sign
+ * change and the lower-right block is -T.  The fields hold, per split:
+ *   inv11   P                      n1 x n1
+ *   rowfac  A21 P                  n2 x n1
+ *   colfac  P A12                  n1 x n2
+ *   negs    N = A21 colfac - A22   n2 x n2
+ *   invn    T = N^-1               n2 x n2
+ *   work    A21 colfac (n2 x n2), later colfac C21 (n1 x n1)            */
+struct split_factors {
+    double *inv11, *rowfac, *colfac, *negs, *invn, *work;
+};
+
+static void factors_free(struct split_factors *f)
+{
+    free(f->inv11);
+    free(f->rowfac);
+    free(f->colfac);
+    free(f->negs);
+    free(f->invn);
+    free(f->work);
+}
+
+static int factors_alloc(struct split_factors *f, int64_t n1, int64_t n2)
+{
+    const int64_t big = n1 > n2 ? n1 : n2;
+    f->inv11 = dalloc(n1, n1);
+    f->rowfac = dalloc(n2, n1);
+    f->colfac = dalloc(n1, n2);
+    f->negs = dalloc(n2, n2);
+    f->invn = dalloc(n2, n2);
+    f->work = dalloc(big, big);
+    return f->inv11 && f->rowfac && f->colfac && f->negs && f->invn && f->work;
+}
+
+/* O2.  C (m x m, ldc) = A^-1.  col0 is the global column offset of this
+ * block, so that a failing leaf reports a global 1-based column.  Every
+ * product is the plain triple loop and every difference a separate rounding,
+ * in the order below: the two factors, the negated Schur complement (product
+ * first, then the difference with A22), its inverse, the two off-diagonal
+ * blocks, the leading block's correction, and the negation of T. */
 static int strassen_rec(const double *A, int64_t m, int64_t lda, double *C, int64_t ldc,
                         int64_t leaf, int64_t col0)
 {
     if (m <= leaf) {
-        int info = oracle_gj_inv(A, m, lda, C, ldc);
+        const int info = oracle_gj_inv(A, m, lda, C, ldc);
         return info > 0 ? (int)(info + col0) : info;
     }
     const int64_t n1 = oracle_split(m), n2 = m - n1;
-    const double *A11 = &AT(A, 0, 0, lda), *A12 = &AT(A, 0, n1, lda);
-    const double *A21 = &AT(A, n1, 0, lda), *A22 = &AT(A, n1, n1, lda);
-    double *C11 = &AT(C, 0, 0, ldc), *C12 = &AT(C, 0, n1, ldc);
-    double *C21 = &AT(C, n1, 0, ldc), *C22 = &AT(C, n1, n1, ldc);
-
-    double *I = dalloc(n1, n1), *II = dalloc(n2, n1), *III = dalloc(n1, n2);
-    double *IV = dalloc(n2, n2), *V = dalloc(n2, n2), *VI = dalloc(n2, n2);
-    double *VII = dalloc(n1, n1);
+    const double *a12 = &AT(A, 0, n1, lda), *a21 = &AT(A, n1, 0, lda), *a22 = &AT(A, n1, n1, lda);
+    double *c11 = &AT(C, 0, 0, ldc), *c12 = &AT(C, 0, n1, ldc);
+    double *c21 = &AT(C, n1, 0, ldc), *c22 = &AT(C, n1, n1, ldc);
+    struct split_factors f;
     int info = -1;
-    if (!I || !II || !III || !IV || !V || !VI || !VII)
-        goto done;
+    if (!factors_alloc(&f, n1, n2))
+        goto out;
 
-    info = strassen_rec(A11, n1, lda, I, n1, leaf, col0);      /* I   = A11^-1   */
+    info = strassen_rec(A, n1, lda, f.inv11, n1, leaf, col0);
     if (info)
-        goto done;
-    oracle_gemm(A21, lda, I, n1, II, n2, n2, n1, n1);           /* II  = A21 I    */
-    oracle_gemm(I, n1, A12, lda, III, n1, n1, n2, n1);          /* III = I A12    */
-    oracle_gemm(A21, lda, III, n1, IV, n2, n2, n2, n1);         /* IV  = A21 III  */
-    mat_sub(IV, n2, A22, lda, V, n2, n2, n2);                   /* V   = IV - A22 */
-    info = strassen_rec(V, n2, n2, VI, n2, leaf, col0 + n1);    /* VI  = V^-1     */
+        goto out;
+    oracle_gemm(a21, lda, f.inv11, n1, f.rowfac, n2, n2, n1, n1);
+    oracle_gemm(f.inv11, n1, a12, lda, f.colfac, n1, n1, n2, n1);
+    oracle_gemm(a21, lda, f.colfac, n1, f.work, n2, n2, n2, n1);
+    mat_sub(f.work, n2, a22, lda, f.negs, n2, n2, n2);
+    info = strassen_rec(f.negs, n2, n2, f.invn, n2, leaf, col0 + n1);
     if (info)
-        goto done;
-    oracle_gemm(III, n1, VI, n2, C12, ldc, n1, n2, n2);         /* C12 = III VI   */
-    oracle_gemm(VI, n2, II, n2, C21, ldc, n2, n1, n2);          /* C21 = VI II    */
-    oracle_gemm(III, n1, C21, ldc, VII, n1, n1, n1, n2);        /* VII = III C21  */
-    mat_sub(I, n1, VII, n1, C11, ldc, n1, n1);                  /* C11 = I - VII  */
-    mat_neg(VI, n2, C22, ldc, n2, n2);                          /* C22 = -VI      */
-done:
-    free(I);
-    free(II);
-    free(III);
-    free(IV);
-    free(V);
-    free(VI);
-    free(VII);
+        goto out;
+    oracle_gemm(f.colfac, n1, f.invn, n2, c12, ldc, n1, n2, n2);
+    oracle_gemm(f.invn, n2, f.rowfac, n2, c21, ldc, n2, n1, n2);
+    oracle_gemm(f.colfac, n1, c21, ldc, f.work, n1, n1, n1, n2);
+    mat_sub(f.inv11, n1, f.work, n1, c11, ldc, n1, n1);
+    mat_neg(f.invn, n2, c22, ldc, n2, n2);
+out:
+    factors_free(&f);
     return info;
 }
 
@@ -250,63 +283,54 @@ static void mat_mirror_lower(double *P, int64_t ldp, int64_t m)
             AT(P, i, j, ldp) = AT(P, j, i, ldp);
 }
 
-/* O3, Alg. 1 specialised to a symmetric A (the positive-definite matrices the
- * paper targets, Sec. 2.1).  With A12 = A21^T and every inverse symmetric,
- * Alg. 1's III = I A12 equals II^T, so
- *   IV  = A21 III = II A12,
- *   C12 = III VI  = (VI II)^T = C21^T,
- *   VII = III C21 = C12 II,
- * and a node needs four products instead of six.  V and C11 are symmetric
- * too: only their lower triangles are kept, mirrored onto the upper ones, so
- * that every block a node passes on (V to the recursion, C11 and C22 to the
- * parent) is exactly symmetric outside the leaves.  Without that, the
- * rounding asymmetry of V and C11 breaks III = II^T at the next level and
- * the residual grows like kappa u.  V-form as in Alg. 1: V = IV - A22,
- * C22 = -VI.  Both triangles of A are read, so the result is the SPD
- * specialisation only for an exactly symmetric A.  The temporaries carry an s
- * suffix (Is = I, IIs = II, ...) to keep them apart from O2's. */
+/* O3: O2 specialised to a symmetric A (the positive-definite matrices the
+ * paper targets, Sec. 2.1).  Then A12 = A21^T and every inverse the recursion
+ * forms is symmetric, so the column factor P A12 is the transpose of the row
+ * factor A21 P and is never formed:
+ *   N   = A21 (P A12) - A22 = rowfac A12 - A22,
+ *   C12 = (P A12) T         = (T rowfac)^T = C21^T,
+ *   C11 = P - (P A12) C21   = P - C12 rowfac,
+ * four products per split instead of six.  N and C11 are symmetric too: only
+ * their lower triangles are kept, mirrored onto the upper ones, so that every
+ * block a split passes on (N to the recursion, C11 and C22 to its caller) is
+ * exactly symmetric outside the leaves.  Passing the rounding asymmetry of N
+ * and C11 on instead would break colfac = rowfac^T one level down, and the
+ * residual would grow like kappa u.  Both triangles of A are read, so this is
+ * the symmetric specialisation only for an exactly symmetric A. */
 static int strassen_spd_rec(const double *A, int64_t m, int64_t lda, double *C, int64_t ldc,
                             int64_t leaf, int64_t col0)
 {
     if (m <= leaf) {
-        int info = oracle_gj_inv(A, m, lda, C, ldc);
+        const int info = oracle_gj_inv(A, m, lda, C, ldc);
         return info > 0 ? (int)(info + col0) : info;
     }
     const int64_t n1 = oracle_split(m), n2 = m - n1;
-    const double *A11 = &AT(A, 0, 0, lda), *A12 = &AT(A, 0, n1, lda);
-    const double *A21 = &AT(A, n1, 0, lda), *A22 = &AT(A, n1, n1, lda);
-    double *C11 = &AT(C, 0, 0, ldc), *C12 = &AT(C, 0, n1, ldc);
-    double *C21 = &AT(C, n1, 0, ldc), *C22 = &AT(C, n1, n1, ldc);
-
-    double *Is = dalloc(n1, n1), *IIs = dalloc(n2, n1), *IVs = dalloc(n2, n2);
-    double *Vs = dalloc(n2, n2), *VIs = dalloc(n2, n2), *VIIs = dalloc(n1, n1);
+    const double *a12 = &AT(A, 0, n1, lda), *a21 = &AT(A, n1, 0, lda), *a22 = &AT(A, n1, n1, lda);
+    double *c11 = &AT(C, 0, 0, ldc), *c12 = &AT(C, 0, n1, ldc);
+    double *c21 = &AT(C, n1, 0, ldc), *c22 = &AT(C, n1, n1, ldc);
+    struct split_factors f;
     int info = -1;
-    if (!Is || !IIs || !IVs || !Vs || !VIs || !VIIs)
-        goto done;
+    if (!factors_alloc(&f, n1, n2))
+        goto out;
 
-    info = strassen_spd_rec(A11, n1, lda, Is, n1, leaf, col0);     /* Is   = A11^-1     */
+    info = strassen_spd_rec(A, n1, lda, f.inv11, n1, leaf, col0);
     if (info)
-        goto done;
-    oracle_gemm(A21, lda, Is, n1, IIs, n2, n2, n1, n1);            /* IIs  = A21 Is     */
-    oracle_gemm(IIs, n2, A12, lda, IVs, n2, n2, n2, n1);           /* IVs  = IIs A12    */
-    mat_sub(IVs, n2, A22, lda, Vs, n2, n2, n2);                    /* Vs   = IVs - A22  */
-    mat_mirror_lower(Vs, n2, n2);                                  /* Vs symmetric      */
-    info = strassen_spd_rec(Vs, n2, n2, VIs, n2, leaf, col0 + n1); /* VIs  = Vs^-1      */
+        goto out;
+    oracle_gemm(a21, lda, f.inv11, n1, f.rowfac, n2, n2, n1, n1);
+    oracle_gemm(f.rowfac, n2, a12, lda, f.work, n2, n2, n2, n1);
+    mat_sub(f.work, n2, a22, lda, f.negs, n2, n2, n2);
+    mat_mirror_lower(f.negs, n2, n2);
+    info = strassen_spd_rec(f.negs, n2, n2, f.invn, n2, leaf, col0 + n1);
     if (info)
-        goto done;
-    oracle_gemm(VIs, n2, IIs, n2, C21, ldc, n2, n1, n2);           /* C21  = VIs IIs    */
-    mat_transpose(C21, ldc, C12, ldc, n2, n1);                     /* C12  = C21^T      */
-    oracle_gemm(C12, ldc, IIs, n2, VIIs, n1, n1, n1, n2);          /* VIIs = C12 IIs    */
-    mat_sub(Is, n1, VIIs, n1, C11, ldc, n1, n1);                   /* C11  = Is - VIIs  */
-    mat_mirror_lower(C11, ldc, n1);                                /* C11 symmetric     */
-    mat_neg(VIs, n2, C22, ldc, n2, n2);                            /* C22  = -VIs       */
-done:
-    free(Is);
-    free(IIs);
-    free(IVs);
-    free(Vs);
-    free(VIs);
-    free(VIIs);
+        goto out;
+    oracle_gemm(f.invn, n2, f.rowfac, n2, c21, ldc, n2, n1, n2);
+    mat_transpose(c21, ldc, c12, ldc, n2, n1);
+    oracle_gemm(c12, ldc, f.rowfac, n2, f.work, n1, n1, n1, n2);
+    mat_sub(f.inv11, n1, f.work, n1, c11, ldc, n1, n1);
+    mat_mirror_lower(c11, ldc, n1);
+    mat_neg(f.invn, n2, c22, ldc, n2, n2);
+out:
+    factors_free(&f);
     return info;
 }
 

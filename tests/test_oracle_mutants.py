@@ -18,38 +18,44 @@ from oracle.exact import exact_inverse, to_float
 SRC = os.path.join(os.path.dirname(oracle.__file__), "spin_oracle.c")
 
 MUTANTS = {
-    "c22_sign": ("mat_neg(VI, n2, C22, ldc, n2, n2);", "mat_copy(VI, n2, C22, ldc, n2, n2);"),
-    "schur_sign": ("mat_sub(IV, n2, A22, lda, V, n2, n2, n2);", "mat_sub(A22, lda, IV, n2, V, n2, n2, n2);"),
-    "ii_transposed": ("oracle_gemm(A21, lda, I, n1, II, n2, n2, n1, n1);",
-                      "oracle_gemm(I, n1, A21, lda, II, n2, n2, n1, n1);"),
-    "c11_dropped_term": ("mat_sub(I, n1, VII, n1, C11, ldc, n1, n1);", "mat_copy(I, n1, C11, ldc, n1, n1);"),
-    "c21_operand_order": ("oracle_gemm(VI, n2, II, n2, C21, ldc, n2, n1, n2);",
-                          "oracle_gemm(II, n2, VI, n2, C21, ldc, n2, n1, n2);"),
+    "c22_sign": ("mat_neg(f.invn, n2, c22, ldc, n2, n2);\nout:\n    factors_free(&f);\n    return info;\n}\n\nint oracle_strassen_inv(",
+                 "mat_copy(f.invn, n2, c22, ldc, n2, n2);\nout:\n    factors_free(&f);\n    return info;\n}\n\nint oracle_strassen_inv("),
+    "schur_sign": ("mat_sub(f.work, n2, a22, lda, f.negs, n2, n2, n2);\n    info = strassen_rec(",
+                   "mat_sub(a22, lda, f.work, n2, f.negs, n2, n2, n2);\n    info = strassen_rec("),
+    "rowfac_transposed": ("oracle_gemm(a21, lda, f.inv11, n1, f.rowfac, n2, n2, n1, n1);\n    oracle_gemm(f.inv11,",
+                          "oracle_gemm(f.inv11, n1, a21, lda, f.rowfac, n2, n2, n1, n1);\n    oracle_gemm(f.inv11,"),
+    "c11_dropped_term": ("mat_sub(f.inv11, n1, f.work, n1, c11, ldc, n1, n1);\n    mat_neg(",
+                         "mat_copy(f.inv11, n1, c11, ldc, n1, n1);\n    mat_neg("),
+    "c21_operand_order": ("oracle_gemm(f.invn, n2, f.rowfac, n2, c21, ldc, n2, n1, n2);\n    oracle_gemm(f.colfac, n1, c21",
+                          "oracle_gemm(f.rowfac, n2, f.invn, n2, c21, ldc, n2, n1, n2);\n    oracle_gemm(f.colfac, n1, c21"),
     "no_row_swap": ("if (p != k)\n            for", "if (0)\n            for"),
     "gemm_k_slip": ("for (int64_t p = 0; p < k; ++p) {", "for (int64_t p = 1; p < k; ++p) {"),
     "scale_left_half_only": ("for (int64_t j = 0; j < w; ++j)\n            AT(M, k, j, n) = AT(M, k, j, n) / piv;",
                              "for (int64_t j = 0; j < n; ++j)\n            AT(M, k, j, n) = AT(M, k, j, n) / piv;"),
     "eliminate_below_only": ("if (i != k)\n                    AT(M, i, j, n)", "if (i > k)\n                    AT(M, i, j, n)"),
-    "second_leaf_offset": ("col0 + n1);    /* VI", "col0);    /* VI"),
+    "second_leaf_offset": ("info = strassen_rec(f.negs, n2, n2, f.invn, n2, leaf, col0 + n1);",
+                           "info = strassen_rec(f.negs, n2, n2, f.invn, n2, leaf, col0);"),
 }
 
 
 # Mistakes planted in O3, the symmetric specialisation.
 SPD_MUTANTS = {
-    "spd_c12_not_transposed": ("mat_transpose(C21, ldc, C12, ldc, n2, n1);",
-                               "mat_copy(C21, ldc, C12, ldc, n1, n2);"),
-    "spd_vii_operand_order": ("oracle_gemm(C12, ldc, IIs, n2, VIIs, n1, n1, n1, n2);",
-                              "oracle_gemm(IIs, n2, C12, ldc, VIIs, n1, n1, n1, n2);"),
-    "spd_iv_uses_a21": ("oracle_gemm(IIs, n2, A12, lda, IVs, n2, n2, n2, n1);",
-                        "oracle_gemm(IIs, n2, A21, lda, IVs, n2, n2, n2, n1);"),
-    "spd_schur_sign": ("mat_sub(IVs, n2, A22, lda, Vs, n2, n2, n2);",
-                       "mat_sub(A22, lda, IVs, n2, Vs, n2, n2, n2);"),
-    "spd_c22_sign": ("mat_neg(VIs, n2, C22, ldc, n2, n2);", "mat_copy(VIs, n2, C22, ldc, n2, n2);"),
-    "spd_c11_dropped_term": ("mat_sub(Is, n1, VIIs, n1, C11, ldc, n1, n1);",
-                             "mat_copy(Is, n1, C11, ldc, n1, n1);"),
-    "spd_second_leaf_offset": ("leaf, col0 + n1); /* VIs", "leaf, col0); /* VIs"),
-    "spd_no_v_mirror": ("    mat_mirror_lower(Vs, n2, n2);", "    (void)0;"),
-    "spd_no_c11_mirror": ("    mat_mirror_lower(C11, ldc, n1);", "    (void)0;"),
+    "spd_c12_not_transposed": ("mat_transpose(c21, ldc, c12, ldc, n2, n1);",
+                               "mat_copy(c21, ldc, c12, ldc, n1, n2);"),
+    "spd_c11_operand_order": ("oracle_gemm(c12, ldc, f.rowfac, n2, f.work, n1, n1, n1, n2);",
+                              "oracle_gemm(f.rowfac, n2, c12, ldc, f.work, n1, n1, n1, n2);"),
+    "spd_schur_uses_a21": ("oracle_gemm(f.rowfac, n2, a12, lda, f.work, n2, n2, n2, n1);",
+                           "oracle_gemm(f.rowfac, n2, a21, lda, f.work, n2, n2, n2, n1);"),
+    "spd_schur_sign": ("mat_sub(f.work, n2, a22, lda, f.negs, n2, n2, n2);\n    mat_mirror_lower(",
+                       "mat_sub(a22, lda, f.work, n2, f.negs, n2, n2, n2);\n    mat_mirror_lower("),
+    "spd_c22_sign": ("mat_neg(f.invn, n2, c22, ldc, n2, n2);\nout:\n    factors_free(&f);\n    return info;\n}\n\nint oracle_strassen_inv_spd(",
+                     "mat_copy(f.invn, n2, c22, ldc, n2, n2);\nout:\n    factors_free(&f);\n    return info;\n}\n\nint oracle_strassen_inv_spd("),
+    "spd_c11_dropped_term": ("mat_sub(f.inv11, n1, f.work, n1, c11, ldc, n1, n1);\n    mat_mirror_lower(",
+                             "mat_copy(f.inv11, n1, c11, ldc, n1, n1);\n    mat_mirror_lower("),
+    "spd_second_leaf_offset": ("info = strassen_spd_rec(f.negs, n2, n2, f.invn, n2, leaf, col0 + n1);",
+                               "info = strassen_spd_rec(f.negs, n2, n2, f.invn, n2, leaf, col0);"),
+    "spd_no_schur_mirror": ("    mat_mirror_lower(f.negs, n2, n2);", "    (void)0;"),
+    "spd_no_c11_mirror": ("    mat_mirror_lower(c11, ldc, n1);", "    (void)0;"),
 }
 
 
