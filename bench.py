@@ -57,8 +57,7 @@ def parse():
     p.add_argument("--seed", type=int, default=None)
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-trace", action="store_true")
-    p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU oracle work")
-    p.add_argument("--serve-seconds", type=float, default=10.0,
+    p.add_argument("--serve-seconds", type=float, default=60.0,
                    help="length of the open-loop serving run (0 disables it)")
     p.add_argument("--serve-rate", type=float, default=200.0, help="serving arrival rate, req/s")
     p.add_argument("--serve-plain", action="store_true",
@@ -89,35 +88,107 @@ def make_input(kind: str, n: int, seed: int):
     return W.spd_spectrum(n, seed, 1e4), f"spd_spectrum (Q diag(lam) Q^T, kappa 1e4), seed {seed}"
 
 
-def cpu_baseline(kind: str, n: int, leaf: int, seed: int, budget_s: float):
-    """Time the oracle's literal Strassen recursion on the host cores: orders
-    1024, 2048, ... up to the workload's own, each run only if the previous
-    one's time scaled by (size ratio)^3 fits the budget left; the largest order
-    run is reported (the workload itself when it fits)."""
+def host_cpu() -> dict:
+    """Model name and core counts of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"model": model, "logical_cpus": os.cpu_count(), "cpus_available": avail}
+
+
+def _omp_threads() -> int:
+    """Threads the oracle's OpenMP loops use by default."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def _set_threads(k: int) -> None:
+    """Thread count of the oracle's OpenMP loops (the oracle links libgomp)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+
+
+def _timed(fn, reps: int) -> float:
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def cpu_baseline(kind: str, n: int, leaf: int, seed: int, a_host, x_gpu):
+    """The CPU oracle on the host cores.
+
+    * value: the oracle's Strassen recursion (O2: the block-inverse identity of
+      Alg. 1 with Gauss-Jordan leaves, FP64, OpenMP) on the workload itself,
+      one run, as 2 n^3 / t;
+    * the GPU result against that oracle inverse: normwise forward error and
+      the largest element-wise error relative to its column's largest entry;
+    * smaller timings: O2 and O1 (Gauss-Jordan with partial pivoting on
+      [A | I]) at n = 1024 and 2048 (O2) on all cores, median of 3, and both
+      at n = 256 and 1024 on one thread.  O1 at the workload's order is not
+      run: its n passes over an n x 2n array make it an hour-scale,
+      memory-bound run."""
+    import numpy as np
+
     import oracle
     lib = oracle.load()
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    sizes = [m for m in (1024, 2048, 4096, 8192, 16384) if m < n] + [n]
-    spent, n_s, t = 0.0, None, None
-    for m in sizes:
-        if t is not None and t * (m / n_s) ** 3 > budget_s - spent:
-            break
-        a, _ = make_input(kind, m, seed)
-        t0 = time.perf_counter()
-        oracle.strassen_inv(a, min(leaf, m), lib)
-        t = time.perf_counter() - t0
-        spent += t
-        n_s = m
-        del a
-    return {
-        "value": 2.0 * n_s ** 3 / t / 1e12,
+    threads = _omp_threads()
+    _set_threads(threads)
+    t0 = time.perf_counter()
+    x_orc, info = oracle.strassen_inv(a_host, min(leaf, n), lib)
+    t = time.perf_counter() - t0
+    out = {
+        "value": 2.0 * n ** 3 / t / 1e12,
         "unit": "TFLOP/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"oracle Strassen recursion (Alg. 1, FP64, OpenMP) on {kind} n={n_s} "
-                  f"leaf={min(leaf, n_s)}" + (" (the whole workload)" if n_s == n else "")
-                  + f": one run, {t:.2f} s ({spent:.1f} s of oracle runs in all)",
+        "sample": f"oracle O2 (Alg. 1 block-inverse recursion with Gauss-Jordan leaves, FP64, OpenMP) "
+                  f"on the whole workload ({kind} n={n} leaf={min(leaf, n)}): one run, {t:.2f} s",
+        "host": host_cpu(),
+        "oracle_info": info,
     }
+    if x_gpu is not None and info == 0:
+        d = np.abs(x_gpu - x_orc)
+        colmax = np.abs(x_orc).max(axis=0)
+        out["forward_error_vs_oracle"] = float(np.linalg.norm(x_gpu - x_orc) / np.linalg.norm(x_orc))
+        out["max_elementwise_error_vs_oracle"] = float((d.max(axis=0) / colmax).max())
+    del x_orc
+    rows = []
+    for m in (1024, 2048):
+        a, _ = make_input(kind, m, seed)
+        rows.append({"oracle": "O2", "n": m, "leaf": min(leaf, m), "threads": threads,
+                     "s_median_of_3": round(_timed(lambda: oracle.strassen_inv(a, min(leaf, m), lib), 3), 4)})
+        if m == 1024:
+            rows.append({"oracle": "O1", "n": m, "threads": threads,
+                         "s_median_of_3": round(_timed(lambda: oracle.gj_inv(a, lib), 3), 4)})
+    _set_threads(1)
+    try:
+        for m in (256, 1024):
+            a, _ = make_input(kind, m, seed)
+            rows.append({"oracle": "O2", "n": m, "leaf": min(leaf, m), "threads": 1,
+                         "s_median_of_3" if m == 256 else "s_one_run":
+                             round(_timed(lambda: oracle.strassen_inv(a, min(leaf, m), lib), 3 if m == 256 else 1), 4)})
+            rows.append({"oracle": "O1", "n": m, "threads": 1,
+                         "s_median_of_3" if m == 256 else "s_one_run":
+                             round(_timed(lambda: oracle.gj_inv(a, lib), 3 if m == 256 else 1), 4)})
+    finally:
+        _set_threads(threads)
+    for r in rows:
+        secs = r.get("s_median_of_3", r.get("s_one_run"))
+        r["gflops_2n3"] = round(2.0 * r["n"] ** 3 / secs / 1e9, 3)
+    out["timings"] = rows
+    return out
 
 
 def serving(rate: float, seconds: float, symmetric: bool = True):
@@ -176,8 +247,8 @@ def mixed_vs_fp64(n: int, leaf: int, reps: int):
         ms = e0.elapsed_time(e1) / reps
         rec = {"ms": round(ms, 2), "ns_steps": steps, "tflops_2n3": round(2.0 * n ** 3 / ms / 1e9, 2)}
         if mode == "fp64":
-            rec["rho"] = spin.residual(dA, dX)
             rec["status"] = spin.info()
+            rec["rho"] = spin.residual(dA, dX)
         else:
             _, rep = spin.invert_mixed(dA, leaf=leaf, mode=mode, ns_steps=steps, out=dX, report=True)
             rec.update(rho_before=rep["rho_before"], rho_after=rep["rho_after"],
@@ -216,8 +287,8 @@ def spd_variant(dA, n: int, leaf: int, steps: int, warmup: int, plain_ms: float)
         "tflops_2n3": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 3),
         "schedule_flops": sched_flops,
         "schedule_tflops": round(sched_flops / (ms * 1e-3) / 1e12, 3),
-        "rho": spin.residual(dA, dX),
         "status": spin.info(),
+        "rho": spin.residual(dA, dX),
     }
     del dX
     return out
@@ -292,7 +363,7 @@ def lu_compare_run():
             ms = C._time_ms(lambda: fn(A, leaf=leaf, out=X), reps=3, warm=1)
             _, fl = spin.plan_describe(n, leaf, **desc)
             row[name] = {"ms": round(ms, 3), "tflops_2n3": round(2.0 * n ** 3 / (ms * 1e-3) / 1e12, 3),
-                         "schedule_flops": fl, "rho": spin.residual(A, X), "status": spin.info()}
+                         "schedule_flops": fl, "status": spin.info(), "rho": spin.residual(A, X)}
             print(f"n={n} {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
         row["lu_over_spin"] = round(row["lu"]["ms"] / row["spin"]["ms"], 3)
         rows.append(row)
@@ -406,7 +477,8 @@ def main():
     a_host, desc = make_input(args.kind, n, seed)
     import numpy as np
     dA = torch.from_numpy(np.ascontiguousarray(a_host.T)).to(dev).t()  # column-major on device
-    del a_host
+    if args.no_cpu:
+        del a_host
     dX = torch.empty_like(dA)
     stream = torch.cuda.current_stream()
 
@@ -487,13 +559,19 @@ def main():
         out["spd_variant"] = spd_variant(dA, n, leaf, args.steps, args.warmup, ms)
     if args.serve_seconds > 0:
         out["serving"] = serving(args.serve_rate, args.serve_seconds, not args.serve_plain)
+    # the timed result itself, compared with the oracle's inverse below
+    x_gpu = dX.cpu().numpy() if not args.no_cpu else None
     if args.mixed_n > 0:
         del dA, dX
         spin.release()
         torch.cuda.empty_cache()
         out["mixed_precision"] = mixed_vs_fp64(args.mixed_n, args.mixed_leaf, args.mixed_reps)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.kind, n, leaf, seed, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.kind, n, leaf, seed, a_host, x_gpu)
+        cb = out["cpu_baseline"]
+        for k in ("forward_error_vs_oracle", "max_elementwise_error_vs_oracle"):
+            if k in cb:
+                out[k] = cb[k]
     print(json.dumps(finite_json(out), allow_nan=False), flush=True)
 
 

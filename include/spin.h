@@ -66,7 +66,10 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
 /* numerical status (positive values come from spin_info / info arrays):      */
 /*   k > 0  : the pivot search for global column k (1-based) found only zero  */
 /*            or non-finite candidates; the inverse is unspecified.           */
-#define SPIN_NS_DIVERGED (-100) /* refinement residual did not decrease       */
+#define SPIN_NS_DIVERGED (-100) /* refinement failed: |I - A X_k|_F did not
+                                   decrease from one Newton step to the next,
+                                   or rho = |A X - I|_F / (|A|_F |X|_F) of the
+                                   refined result is above 1e-12 (or NaN)     */
 
 #define SPIN_MAX_LEAF 2048
 #define SPIN_MAX_N (1 << 20)
@@ -93,6 +96,12 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
  * result bit for bit, a mixed mode spin_invert_mixed's with the flag).
  * Anywhere else, or with an unknown mode, it is SPIN_E_MODE. */
 #define SPIN_SYMMETRIC 16
+/* Refinement flag, OR-ed into a mixed mode of spin_invert_mixed only: the
+ * Newton residual R = I - A X, the update X + X R and the acceptance
+ * residual are formed by spin_gemm_int8's emulation (14 moduli, operands
+ * rounded to 47 bits per row / column at order 16384, more below) instead of
+ * FP64 matrix cores.  The batched and serving entry points reject it. */
+#define SPIN_REFINE_INT8 32
 
 /* ---- FP64 inversion ------------------------------------------------------- */
 /* Ainv (n x n, ldx) := A^-1 for A (n x n, lda), FP64 throughout.
@@ -150,6 +159,10 @@ typedef struct spin_report {
  * leaves, followed by `ns_steps` (0..8) FP64 Newton steps
  *     R = I - A X,  X <- X + X R
  * (Newton iteration as the stabiliser of Strassen inversion, Sec. 2.1).
+ * When ns_steps > 0 the call also accepts or rejects the refined result on
+ * the device: one more FP64 product forms R = I - A X, and unless
+ * rho = |R|_F / (|A|_F |X|_F) <= 1e-12 the status (spin_info) becomes
+ * SPIN_NS_DIVERGED; the result stays in Ainv either way.
  * mode | SPIN_SYMMETRIC (exactly symmetric A) runs the recursion on the
  * symmetric schedule of spin_invert_spd, about half the block-product work;
  * the refinement is unchanged.  If `rep` is non-NULL the call waits for the stream, evaluates both residuals
@@ -175,6 +188,32 @@ int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha,
               const void *A, int64_t lda, const void *B, int64_t ldb, double beta,
               const void *C0, int64_t ldc, void *D, int64_t ldd, int add_identity,
               spin_stream_t stream);
+
+/* ---- FP64-accurate product on INT8 matrix cores --------------------------- */
+/* D (m x n, ldd) := epilogue(A (m x k, lda) * B (k x n, ldb)), FP64 operands
+ * and result, column-major, computed on INT8 matrix cores by the integer
+ * modular scheme of Ozaki, Uchino and Imamura (Ozaki scheme II, 2025): row i
+ * of A is scaled by a power of two and rounded to an integer of at most
+ * beta_a bits (nearest, ties to even; the row's largest magnitude sets the
+ * scale), column j of B likewise to beta_b bits; the integer product is
+ * formed exactly from `moduli` INT8 residue products (2 <= moduli <= 15,
+ * pairwise coprime moduli 256, 255, 253, 251, 247, 241, 239, 233, ...) and
+ * Chinese remaindering, rounded once to FP64 and scaled back.  This is the
+ * product the Newton refinement needs in FP64 (Newton iteration as the
+ * stabiliser of Strassen inversion, Sec. 2.1).
+ *   epilogue 0: D = A B;  1: D = I - A B (m == n);  2: D = C0 + A B (C0 may
+ *               equal D, each element is read before it is written).
+ *   beta_a, beta_b <= 0: the largest equal pair the moduli allow at this k
+ *   (at most 53).  Otherwise 1 + log2(k) + beta_a + beta_b must stay below
+ *   log2 of the product of the moduli (SPIN_E_MODE).
+ * Error against the exact product: |D - A B| <= 2^-beta (m_i sum_k |b_kj| +
+ * n_j sum_k |a_ik|) + k 2^-2beta m_i n_j + 2^-53 |D| before the epilogue
+ * (m_i, n_j: the largest magnitudes of row i of A and column j of B).  A row
+ * of A or a column of B holding Inf or NaN gives NaN in its row / column.
+ * Uses the stream's workspace (about 3 moduli m n bytes); asynchronous. */
+int spin_gemm_int8(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
+                   int64_t ldb, int epilogue, const double *C0, int64_t ldc, double *D, int64_t ldd,
+                   int moduli, int beta_a, int beta_b, spin_stream_t stream);
 
 /* ---- status and residual -------------------------------------------------- */
 /* Waits for `stream` and returns the numerical status of the last inversion

@@ -52,7 +52,9 @@ int oracle_version(void) { return 1; }
 void oracle_gemm(const double *A, int64_t lda, const double *B, int64_t ldb,
                  double *C, int64_t ldc, int64_t m, int64_t n, int64_t k)
 {
-#pragma omp parallel for schedule(static)
+    /* threads only for products large enough to repay their start-up; each
+     * column is the same sum either way */
+#pragma omp parallel for schedule(static) if ((double)m * (double)n * (double)k > 4.0e6)
     for (int64_t j = 0; j < n; ++j) {
         for (int64_t i = 0; i < m; ++i)
             AT(C, i, j, ldc) = 0.0;
@@ -119,7 +121,7 @@ int oracle_gj_inv(const double *A, int64_t n, int64_t lda, double *X, int64_t ld
          * row_i <- row_i - M[i,k] * row_k, with M[i,k] taken before the step */
         for (int64_t i = 0; i < n; ++i)
             f[i] = AT(M, i, k, n);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if ((double)n * (double)w > 2.0e5)
         for (int64_t j = 0; j < w; ++j) {
             const double rk = AT(M, k, j, n);
             for (int64_t i = 0; i < n; ++i)

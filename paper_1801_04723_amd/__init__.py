@@ -31,11 +31,16 @@ MIXED_BF16X3 = 3
 # server_request_bytes: the recursion runs the symmetric schedule of invert_spd
 # (exactly symmetric inputs only).
 SYMMETRIC = 16
+# Flag OR-ed into a mixed mode of invert_mixed: the refinement's products run
+# on INT8 matrix cores (gemm_int8).
+REFINE_INT8 = 32
 MODES = {"fp64": FP64, "fp32": MIXED_FP32, "mixed_fp32": MIXED_FP32,
          "bf16": MIXED_BF16, "mixed_bf16": MIXED_BF16,
          "bf16x3": MIXED_BF16X3, "mixed_bf16x3": MIXED_BF16X3,
          "fp64_sym": FP64 | SYMMETRIC, "fp32_sym": MIXED_FP32 | SYMMETRIC,
-         "bf16_sym": MIXED_BF16 | SYMMETRIC, "bf16x3_sym": MIXED_BF16X3 | SYMMETRIC}
+         "bf16_sym": MIXED_BF16 | SYMMETRIC, "bf16x3_sym": MIXED_BF16X3 | SYMMETRIC,
+         "fp32_int8": MIXED_FP32 | REFINE_INT8, "bf16x3_int8": MIXED_BF16X3 | REFINE_INT8,
+         "bf16_int8": MIXED_BF16 | REFINE_INT8}
 NS_DIVERGED = -100
 MAX_LEAF = 2048
 
@@ -113,6 +118,9 @@ def lib() -> ctypes.CDLL:
         L.spin_gemm.argtypes = [ctypes.c_int, _i64, _i64, _i64, ctypes.c_double, _vp, _i64, _vp, _i64,
                                 ctypes.c_double, _vp, _i64, _vp, _i64, ctypes.c_int, _vp]
         L.spin_gemm.restype = ctypes.c_int
+        L.spin_gemm_int8.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _vp, _i64, _vp,
+                                     _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp]
+        L.spin_gemm_int8.restype = ctypes.c_int
         L.spin_info.argtypes = [_vp]
         L.spin_info.restype = ctypes.c_int
         L.spin_residual.argtypes = [_vp, _i64, _i64, _vp, _i64, ctypes.POINTER(ctypes.c_double), _vp]
@@ -368,6 +376,19 @@ def gemm_cm(m, n, k, alpha, A, lda, B, ldb, beta, C0, ldc, D, ldd, add_identity=
                          ptr(C0), ldc, ptr(D), ldd, 1 if add_identity else 0, _stream(stream))
     if rc != 0:
         raise SpinError(rc, "spin_gemm")
+
+
+def gemm_int8(m, n, k, A, lda, B, ldb, epilogue, C0, ldc, D, ldd, moduli: int = 14, beta_a: int = 0,
+              beta_b: int = 0, stream=None):
+    """spin_gemm_int8 on column-major float64 GPU buffers: D = A B (epilogue 0),
+    I - A B (1) or C0 + A B (2), FP64-accurate on INT8 matrix cores."""
+    ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+    rc = lib().spin_gemm_int8(int(m), int(n), int(k), ptr(A), int(lda), ptr(B), int(ldb), int(epilogue),
+                              ptr(C0), int(ldc), ptr(D), int(ldd), int(moduli), int(beta_a), int(beta_b),
+                              _stream(stream))
+    if rc != 0:
+        raise SpinError(rc, "spin_gemm_int8")
+    return D
 
 
 def info(stream=None) -> int:

@@ -11,8 +11,9 @@ namespace {
 
 constexpr int kNormBlocks = 1024;
 
-__global__ void k_status_reset(int *status, int n) {
-    if ((int)threadIdx.x < n) status[threadIdx.x] = INT_MAX;
+__global__ void k_status_reset(int *status, int spec) {
+    const int i = threadIdx.x;
+    if (i < kStatusWords) status[i] = (i == kStatusSpecWord && !spec) ? 0 : INT_MAX;
 }
 
 // 2-D grid-stride conversion of an (m x n) column-major view.
@@ -122,6 +123,16 @@ __global__ void k_ns_check(const double *norms, int j, int *status) {
     if (threadIdx.x == 0 && j > 0 && !(norms[j] < norms[j - 1])) status[0] = kStatusNsDiverged;
 }
 
+// Acceptance of a refined inverse: flags divergence unless
+// rho = |R|_F / (|A|_F |X|_F) <= tol (a NaN anywhere fails the test).
+__global__ void k_ns_final(const double *r2, const double *a2, const double *x2, double tol,
+                           int *status) {
+    if (threadIdx.x == 0) {
+        const double rho = sqrt(*r2) / (sqrt(*a2) * sqrt(*x2));
+        if (!(rho <= tol)) status[0] = kStatusNsDiverged;
+    }
+}
+
 template <typename S, typename D>
 hipError_t convert(const S *src, int64_t lds, D *dst, int64_t ldd, int64_t m, int64_t n,
                    hipStream_t s) {
@@ -134,8 +145,8 @@ hipError_t convert(const S *src, int64_t lds, D *dst, int64_t ldd, int64_t m, in
 
 }  // namespace
 
-hipError_t status_reset(int *status, int n_words, hipStream_t s) {
-    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, s, status, n_words);
+hipError_t status_reset(int *status, bool spec, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, s, status, spec ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -182,6 +193,12 @@ hipError_t transpose_f64(const double *src, int64_t lds, double *dst, int64_t ld
 
 hipError_t ns_check(const double *norms, int j, int *status, hipStream_t s) {
     hipLaunchKernelGGL(k_ns_check, dim3(1), dim3(64), 0, s, norms, j, status);
+    return hipGetLastError();
+}
+
+hipError_t ns_final(const double *r2, const double *a2, const double *x2, double tol, int *status,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_ns_final, dim3(1), dim3(64), 0, s, r2, a2, x2, tol, status);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Leaf inversion: Gauss-Jordan elimination with partial pivoting in FP64.
 //
-// The paper inverts each leaf block "in any approach" on a single node
-// (Alg. 1, Alg. 2 `locInverse`, Sec. 3.3); here it is Gauss-Jordan with
+// The paper leaves the method of the leaf inversion open and runs it on a
+// single node (Alg. 1, Alg. 2 `locInverse`, Sec. 3.3); here it is Gauss-Jordan with
 // partial pivoting, always in FP64 (also when the surrounding products run in
 // FP32).
 //
@@ -110,6 +110,10 @@ struct LeafArgs {
     int k0, nb;
     int *used, *rsel;
     double *Up, *Q;
+    // Speculation switch of the inversion (nullable): nonzero lets the kernel
+    // try the speculative elimination first; a failed attempt sets it to 0 so
+    // that the later leaves of the same inversion go straight to the search.
+    int *spec;
 };
 
 template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
@@ -323,9 +327,231 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
     if (t == 0 && bad) atomicMin(a.status, a.col0 + k0 + bad);
 }
 
+// ------------------------------------------------ speculative 2-D kernel ---
+// The elimination of gj2d_run for blocks whose partial-pivoting choice at
+// step k is row k itself, as it is at every step for strictly diagonally
+// dominant blocks (their Schur complements stay dominant) and, in practice,
+// for well-conditioned positive-definite ones.  Each step takes that row as
+// its pivot and checks the choice exactly: the step stands when the pivot is
+// finite and nonzero and no unused row holds a larger magnitude or a
+// non-finite value.  As long as every earlier step stood, the unused rows are
+// exactly the rows below the pivot, so a tie goes to the pivot row, which is
+// what the search's smallest-index rule picks.
+//
+// With the pivot row known in advance the search leaves the dependent chain,
+// and so does one barrier: once step c is applied, the owners of column c+1
+// publish its multipliers and the owners of row c+1 the pivot row (whole
+// leaves: scaled, since the pivot row's wave also holds the pivot; panels:
+// raw, with the inverse pivot published by the pivot's owner), and after one
+// barrier every thread applies step c+1.  Every element goes through the
+// same operations as in gj2d_run (the same division, products and fused
+// multiply-adds), so when every check passes the outputs are gj2d_run's bit
+// for bit.  They are written only then.  Returns whether every check passed
+// (the same in every thread); on false nothing has been written.
+template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
+__device__ __attribute__((always_inline)) inline bool gj2d_spec(const LeafArgs &a) {
+    constexpr int NT = 16 * TR;
+    constexpr int LMAX = TR * RR;
+    constexpr int NBMAX = 16 * RC;
+    static_assert(TR == 16 || TR == 32, "row groups of 16 or 32 threads");
+    // Shared arrays are indexed by register slot, not by row: entry tr + TR r
+    // belongs to slot r of the threads with that tr (the same map in every
+    // thread), so that every access is a per-thread base plus a constant.
+    __shared__ double fbs[2][LMAX];   // multipliers of a step, -1 / 0 at its pivot row
+    __shared__ double rws[2][NBMAX];  // its pivot row (see above)
+    __shared__ double pvs[2][2];      // |pivot| (whole leaves) and 1 / pivot (panels)
+    const int t = threadIdx.x, wave = t >> 6;
+    const int tr = WHOLE ? t >> 4 : t % TR, tc = WHOLE ? t & 15 : t / TR;
+    const int L = a.L;
+    const int k0 = WHOLE ? 0 : a.k0;
+    const int nb = WHOLE ? a.L : a.nb;
+    const double *src = WHOLE ? nullptr : (a.in ? static_cast<const double *>(a.in) : a.Z);
+    const int64_t lds = WHOLE ? 0 : (a.in ? a.ldi : a.ldz);
+    // Register slot r holds row tr + TR ((r + rot) mod RR), rot = k0 / TR: the
+    // row map turns with the panel's first column (a multiple of TR), so that
+    // the pivot row of step c (row k0 + c) sits in slot c / TR of thread
+    // c mod TR, a constant of the unrolled column block cb = c / 16.  Slots
+    // r >= RR - rot hold the rows before the panel, all of them used.
+    const int rot = k0 / TR;
+    int rowr[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) rowr[r] = tr + TR * ((r + rot) % RR);
+
+    double z[RR][RC];
+    bool viol = !WHOLE && (k0 % TR) != 0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+        const int row = rowr[r];
+        // the rows before the panel must be the used ones and no other
+        if (!WHOLE && k0 > 0 && row < L && ((a.used[row] != 0) != (row < k0))) viol = true;
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            const int col = tc + 16 * q;
+            double v = 0.0;
+            if (row < L && col < nb) {
+                if (WHOLE)
+                    v = (double)static_cast<const TI *>(a.in)[row + (int64_t)col * a.ldi];
+                else
+                    v = src[row + (int64_t)(k0 + col) * lds];
+            }
+            z[r][q] = v;
+        }
+    }
+    double *const fbt = &fbs[0][tr];
+    double *const rwt = &rws[0][tc];
+
+    // One step c = 16 cb + cc, LDS buffer B = c & 1: publication (its column
+    // and pivot row are final once step c - 1 is applied), one barrier, the
+    // update.  cb and B are constants after unrolling.
+    auto step = [&](const int cb, const int cc, const int B) {
+        const int c = 16 * cb + cc, p = k0 + c;
+        const int PR = (16 * cb) / TR;          // register slot of the pivot row
+        const int pt = (16 * cb) % TR + cc;     // its owners' tr
+        if (WHOLE) {
+            // the 16 owners of row p are lanes 16 pt .. 16 pt + 15 of one wave
+            if (wave == (16 * pt) >> 6) {
+                const double piv = readlane_f64(z[PR][cb], (16 * pt + cc) & 63);
+                if (tr == pt) {
+                    const double pinv = 1.0 / piv;
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) {
+                        rwt[B * NBMAX + 16 * q] = (q == cb && tc == cc) ? pinv : z[PR][q] * pinv;
+                        z[PR][q] = 0.0;  // the update adds the scaled row (multiplier -1)
+                    }
+                    if (tc == cc) pvs[B][0] = fabs(piv);
+                }
+            }
+            if (tc == cc) {
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    fbt[B * LMAX + TR * r] = (r == PR && tr == pt) ? -1.0 : z[r][cb];
+                    z[r][cb] = 0.0;
+                }
+            }
+        } else {
+            if (tr == pt) {
+#pragma unroll
+                for (int q = 0; q < RC; ++q)
+                    rwt[B * NBMAX + 16 * q] = (q == cb && tc == cc) ? 1.0 : z[PR][q];
+                if (tc == cc) pvs[B][1] = 1.0 / z[PR][cb];
+            }
+            // the owners of column c (half of wave cc / 2 when TR = 32) also
+            // check the step: the pivot, read from its lane, against every
+            // unused row they hold
+            if (wave == (TR * cc) >> 6) {
+                const double piv = readlane_f64(z[PR][cb], (TR * cc + pt) & 63);
+                const double apiv = fabs(piv);
+                bool v = !(apiv > 0.0) || !(apiv <= DBL_MAX);
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    if (r < PR) continue;  // rows before the pivot: used
+                    const bool used = (r == PR) ? (tr <= pt) : (r + rot >= RR);
+                    v = v || (!used && !(fabs(z[r][cb]) <= apiv));
+                }
+                if (tc == cc) viol = viol || v;
+            }
+            if (tc == cc) {
+#pragma unroll
+                for (int r = 0; r < RR; ++r) {
+                    fbt[B * LMAX + TR * r] = (r == PR && tr == pt) ? 0.0 : z[r][cb];
+                    z[r][cb] = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+        double f[RR], rv[RC];
+#pragma unroll
+        for (int r = 0; r < RR; ++r) f[r] = fbt[B * LMAX + TR * r];
+#pragma unroll
+        for (int q = 0; q < RC; ++q) rv[q] = rwt[B * NBMAX + 16 * q];
+        if (WHOLE) {
+            // check of step c: the pivot, then the unused rows of this thread
+            const double apiv = pvs[B][0];
+            bool v = !(apiv > 0.0) || !(apiv <= DBL_MAX);
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                if (r < PR) continue;  // rows before the pivot: used
+                const bool used = (r == PR) && (tr <= pt);
+                v = v || (!used && !(fabs(f[r]) <= apiv));
+            }
+            viol = viol || v;
+        } else {
+            const double pinv = pvs[B][1];
+#pragma unroll
+            for (int q = 0; q < RC; ++q) rv[q] = rv[q] * pinv;
+            if (tr == pt) {
+#pragma unroll
+                for (int q = 0; q < RC; ++q) z[PR][q] = rv[q];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+            for (int q = 0; q < RC; ++q) z[r][q] = fma(-f[r], rv[q], z[r][q]);
+    };
+
+#pragma unroll
+    for (int cb = 0; cb < RC; ++cb) {
+        for (int cc = 0; cc < 16; cc += 2) {
+            if (16 * cb + cc >= nb) break;
+            step(cb, cc, 0);
+            if (16 * cb + cc + 1 >= nb) break;
+            step(cb, cc + 1, 1);
+        }
+    }
+    if (__syncthreads_or(viol)) return false;
+
+    if (WHOLE) {
+        TO *out = static_cast<TO *>(a.out);
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+                const int row = rowr[r], col = tc + 16 * q;
+                if (row < L && col < L) out[row + (int64_t)col * a.ldo] = (TO)z[r][q];
+            }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+            for (int q = 0; q < RC; ++q) {
+                const int row = rowr[r], col = tc + 16 * q;
+                if (row < L && col < nb) {
+                    a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[r][q];
+                    a.Up[row + (int64_t)col * L] = z[r][q] - ((row == k0 + col) ? 1.0 : 0.0);
+                }
+            }
+        for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = k0 + c;
+        for (int row = t; row < L; row += NT) {
+            const bool piv = row >= k0 && row < k0 + nb;
+            if (k0 == 0)
+                a.used[row] = piv ? 1 : 0;
+            else if (piv)
+                a.used[row] = 1;
+        }
+        // pivot rows of the columns outside the panel: rows k0 .. k0 + nb - 1
+        const int nout = L - nb;
+        for (int e = t; e < nb * nout; e += NT) {
+            const int c = e % nb, j = e / nb;
+            const int gj = j < k0 ? j : j + nb;
+            a.Q[c + (int64_t)gj * nb] = src[(k0 + c) + (int64_t)gj * lds];
+        }
+    }
+    return true;
+}
+
+template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
+__device__ __attribute__((always_inline)) inline void gj2d_any(const LeafArgs &a) {
+    if (a.spec && *a.spec != 0) {
+        if (gj2d_spec<TR, RR, RC, WHOLE, TI, TO>(a)) return;
+        if (threadIdx.x == 0) *a.spec = 0;
+    }
+    gj2d_run<TR, RR, RC, WHOLE, TI, TO>(a);
+}
+
 template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
 __global__ void __launch_bounds__(16 * TR) leaf_gj2d(LeafArgs a) {
-    gj2d_run<TR, RR, RC, WHOLE, TI, TO>(a);
+    gj2d_any<TR, RR, RC, WHOLE, TI, TO>(a);
 }
 
 // Many independent whole leaves in one grid (one workgroup each); the same
@@ -342,7 +568,8 @@ __global__ void __launch_bounds__(16 * TR) leaf_gj2d_batch(LeafBatch b) {
     a.L = (int)it.L;
     a.col0 = (int)it.col0;
     a.status = it.status;
-    gj2d_run<TR, RR, RC, true, TI, TO>(a);
+    a.spec = it.status + kStatusSpecWord;
+    gj2d_any<TR, RR, RC, true, TI, TO>(a);
 }
 
 // ---------------------------------------------------------------- tier 2 ---
@@ -607,6 +834,7 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
         la.L = L;
         la.col0 = (int)col0;
         la.status = status;
+        la.spec = status + kStatusSpecWord;
         hipError_t e;
         const char *name = "leaf_gj_regs";
         if (in_dt == kF64 && out_dt == kF64)
@@ -662,6 +890,7 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                 la.L = L;
                 la.col0 = (int)col0;
                 la.status = status;
+                la.spec = status + kStatusSpecWord;
                 la.Z = Z;
                 la.ldz = L;
                 la.k0 = k0;

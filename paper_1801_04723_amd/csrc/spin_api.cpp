@@ -437,6 +437,9 @@ hipStream_t g_capture = nullptr;
 // Largest number of cached graphs (one per mode, shape, buffer set and stream
 // workspace) before the cache is emptied.
 constexpr size_t kMaxGraphs = 64;
+// Added to a graph key's entry-point id when leaves skip the speculative
+// elimination.
+constexpr int kNoSpecKey = 1 << 12;
 
 void drop_graphs_for(void *base) {
     for (auto it = g_graphs.begin(); it != g_graphs.end();) {
@@ -453,17 +456,31 @@ void drop_graphs_for(void *base) {
 int ws_acquire(hipStream_t s, size_t bytes, Workspace **out) {
     Workspace &w = g_ws[s];
     if (w.bytes < bytes) {
-        if (w.base) {
-            hipStreamSynchronize(s);
-            drop_graphs_for(w.base);
-            hipFree(w.base);
-            w.base = nullptr;
-            w.bytes = 0;
-        }
         void *p = nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess || !p) {
             (void)hipGetLastError();
             return SPIN_E_NOMEM;
+        }
+        if (w.base) {
+            // the status words of the last call on the stream move along, so
+            // that spin_info still reports it after a later call grew the
+            // workspace without writing them (spin_residual)
+            hipError_t e = hipMemcpyAsync(p, w.base, 256, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                hipFree(p);
+                return SPIN_E_HIP;
+            }
+            drop_graphs_for(w.base);
+            hipFree(w.base);
+        } else {
+            // a fresh workspace reports "no event" until an inversion runs
+            if (status_reset(static_cast<int *>(p), true, s) != hipSuccess) {
+                (void)hipGetLastError();
+                hipFree(p);
+                return SPIN_E_HIP;
+            }
         }
         w.base = static_cast<char *>(p);
         w.bytes = bytes;
@@ -560,6 +577,17 @@ int validate(const void *A, int64_t n, int64_t lda, const void *X, int64_t ldx, 
     return SPIN_OK;
 }
 
+}  // namespace
+
+// Whether leaves try the speculative elimination first (SPIN_NO_SPEC=1 turns
+// it off; the results are the same either way).
+bool leaf_spec_enabled() {
+    const char *e = std::getenv("SPIN_NO_SPEC");
+    return !(e && e[0] && e[0] != '0');
+}
+
+namespace {
+
 bool graphs_enabled() {
     const char *e = std::getenv("SPIN_NO_GRAPH");
     return !(e && e[0] && e[0] != '0') && !g_trace_on;
@@ -634,14 +662,15 @@ int spin_invert(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t l
     if (rc) return rc;
     Exec E{s, {(char *)A, (char *)Ainv, w->base + L.rec_off}, 8, kF64, status_ptr(w),
            w->base + L.leaf_off};
+    const bool spec = leaf_spec_enabled();
     auto body = [&](hipStream_t qs) -> hipError_t {
         Exec Eq = E;
         Eq.s = qs;
-        hipError_t e = status_reset(Eq.status, 2, qs);
+        hipError_t e = status_reset(Eq.status, spec, qs);
         if (e != hipSuccess) return e;
         return run_plan(P, Eq);
     };
-    return run_maybe_graph(std::make_tuple(0, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
+    return run_maybe_graph(std::make_tuple(spec ? 0 : kNoSpecKey, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
                                            (void *)w->base, 0),
                            s, body);
 }
@@ -659,14 +688,15 @@ int spin_invert_spd(const double *A, int64_t n, int64_t lda, double *Ainv, int64
     if (rc) return rc;
     Exec E{s, {(char *)A, (char *)Ainv, w->base + L.rec_off}, 8, kF64, status_ptr(w),
            w->base + L.leaf_off};
+    const bool spec = leaf_spec_enabled();
     auto body = [&](hipStream_t qs) -> hipError_t {
         Exec Eq = E;
         Eq.s = qs;
-        hipError_t e = status_reset(Eq.status, 2, qs);
+        hipError_t e = status_reset(Eq.status, spec, qs);
         if (e != hipSuccess) return e;
         return run_plan(P, Eq);
     };
-    return run_maybe_graph(std::make_tuple(2, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
+    return run_maybe_graph(std::make_tuple(spec ? 2 : 2 + kNoSpecKey, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
                                            (void *)w->base, 0),
                            s, body);
 }
@@ -685,14 +715,15 @@ int spin_invert_lu(const double *A, int64_t n, int64_t lda, double *Ainv, int64_
     if (rc) return rc;
     Exec E{s, {(char *)A, (char *)Ainv, w->base + L.rec_off}, 8, kF64, status_ptr(w),
            w->base + L.leaf_off};
+    const bool spec = leaf_spec_enabled();
     auto body = [&](hipStream_t qs) -> hipError_t {
         Exec Eq = E;
         Eq.s = qs;
-        hipError_t e = status_reset(Eq.status, 2, qs);
+        hipError_t e = status_reset(Eq.status, spec, qs);
         if (e != hipSuccess) return e;
         return run_plan(P, Eq);
     };
-    return run_maybe_graph(std::make_tuple(3, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
+    return run_maybe_graph(std::make_tuple(spec ? 3 : 3 + kNoSpecKey, n, lda, ldx, leaf, (const void *)A, (void *)Ainv,
                                            (void *)w->base, 0),
                            s, body);
 }
@@ -702,9 +733,11 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
                       spin_stream_t stream) {
     int rc = validate(A, n, lda, Ainv, ldx, leaf);
     if (rc) return rc;
-    // SPIN_SYMMETRIC: the symmetric schedule with the mode's product flavour
+    // SPIN_SYMMETRIC: the symmetric schedule with the mode's product flavour;
+    // SPIN_REFINE_INT8: the refinement's products emulated on INT8 cores
     const bool sym = (mode & SPIN_SYMMETRIC) != 0;
-    const int pmode = mode & ~SPIN_SYMMETRIC;
+    const bool emu = (mode & SPIN_REFINE_INT8) != 0;
+    const int pmode = mode & ~(SPIN_SYMMETRIC | SPIN_REFINE_INT8);
     if (!is_mixed_mode(pmode) || ns_steps < 0 || ns_steps > kNormSlots) return SPIN_E_MODE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(g_mu);
@@ -712,10 +745,28 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
     // FP32 storage has no mirror or transpose kernel of its own
     if (!plan_folds_all(P)) return SPIN_E_MODE;
     Layout L = layout_for(n, leaf, pmode, P.ws_elems, P.max_leaf);
+    const size_t oz_off = L.total;
+    const int oz_beta = std::min(53, ozaki_beta(kRefineModuli, n));
+    const size_t oz_bytes = emu ? ozaki_workspace_bytes(n, n, n, kRefineModuli) : 0;
     Workspace *w = nullptr;
-    rc = ws_acquire(s, L.total, &w);
+    rc = ws_acquire(s, oz_off + oz_bytes, &w);
     if (rc) return rc;
     char *base = w->base;
+    // residual / update product of the refinement: FP64 matrix cores, or
+    // the INT8 emulation (epilogue 1: I - P, 2: C0 + P)
+    auto refine_product = [&](const double *pa, int64_t la, const double *pb, int64_t lb, int epi,
+                              const double *c0, int64_t lc, double *d, int64_t ld, hipStream_t qs,
+                              LaunchInfo *li) -> hipError_t {
+        if (emu) {
+            OzakiProb op{pa, la, pb, lb, c0, lc, d, ld, n, n, n, epi, kRefineModuli, oz_beta, oz_beta};
+            if (li) *li = LaunchInfo{"gemm_int8_emulated", 2.0 * n * (double)n * n, 24.0 * n * (double)n};
+            return ozaki_product(op, base + oz_off, qs);
+        }
+        GemmProb pr{pa, pb, epi == 2 ? c0 : nullptr, d, la, lb, epi == 2 ? lc : 1, ld,
+                    (int32_t)n, (int32_t)n, (int32_t)n, epi == 1 ? 1 : 0, epi == 1 ? -1.0 : 1.0,
+                    epi == 2 ? 1.0 : 0.0};
+        return gemm_launch(&pr, 1, kF64, qs, li);
+    };
     float *A32 = reinterpret_cast<float *>(base + L.a32_off);
     float *X32 = reinterpret_cast<float *>(base + L.x32_off);
     double *R = reinterpret_cast<double *>(base + L.r_off);
@@ -729,8 +780,9 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
     double *buf1 = (ns_steps % 2 == 0) ? Xalt : Ainv;
     const int64_t ld1 = (ns_steps % 2 == 0) ? n : ldx;
 
+    const bool spec = leaf_spec_enabled();
     auto body = [&](hipStream_t qs) -> hipError_t {
-        hipError_t e = status_reset(status, 2, qs);
+        hipError_t e = status_reset(status, spec, qs);
         if (e != hipSuccess) return e;
         e = cast_f64_to_f32(A, lda, A32, n, n, n, qs);
         if (e != hipSuccess) return e;
@@ -747,11 +799,9 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
             const int64_t ldn = (j % 2 == 0) ? ld1 : ld0;
             TraceCtx ctx{qs, -1, nullptr};
             // R = I - A X
-            GemmProb pr{A, xc, nullptr, R, lda, ldc, 1, n, (int32_t)n, (int32_t)n, (int32_t)n,
-                        1, -1.0, 0.0};
             LaunchInfo li{};
             if (g_trace_on) trace_cb(&ctx, li, 0);
-            e = gemm_launch(&pr, 1, kF64, qs, &li);
+            e = refine_product(A, lda, xc, ldc, 1, nullptr, 1, R, n, qs, &li);
             if (g_trace_on) trace_cb(&ctx, li, 1);
             if (e != hipSuccess) return e;
             e = frob2(R, n, n, n, parts, norms + j, qs);
@@ -759,44 +809,53 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
             e = ns_check(norms, j, status + 1, qs);
             if (e != hipSuccess) return e;
             // X' = X + X R
-            GemmProb pu{xc, R, xc, xn, ldc, n, ldc, ldn, (int32_t)n, (int32_t)n, (int32_t)n,
-                        0, 1.0, 1.0};
             if (g_trace_on) trace_cb(&ctx, li, 0);
-            e = gemm_launch(&pu, 1, kF64, qs, &li);
+            e = refine_product(xc, ldc, R, n, 2, xc, ldc, xn, ldn, qs, &li);
             if (g_trace_on) trace_cb(&ctx, li, 1);
+            if (e != hipSuccess) return e;
+        }
+        if (ns_steps > 0) {
+            // acceptance of the refined inverse (now in Ainv): rho <= kNsTol
+            double *misc = norms + kNormSlots;  // 0: |A|^2, 2: |R_final|^2, 3: |X|^2
+            TraceCtx ctx{qs, -1, nullptr};
+            LaunchInfo li{};
+            if (g_trace_on) trace_cb(&ctx, li, 0);
+            e = refine_product(A, lda, Ainv, ldx, 1, nullptr, 1, R, n, qs, &li);
+            if (g_trace_on) trace_cb(&ctx, li, 1);
+            if (e == hipSuccess) e = frob2(R, n, n, n, parts, misc + 2, qs);
+            if (e == hipSuccess) e = frob2(A, lda, n, n, parts, misc + 0, qs);
+            if (e == hipSuccess) e = frob2(Ainv, ldx, n, n, parts, misc + 3, qs);
+            if (e == hipSuccess) e = ns_final(misc + 2, misc + 0, misc + 3, kNsTol, status + 1, qs);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };
-    rc = run_maybe_graph(std::make_tuple(1 + 16 * mode, n, lda, ldx, leaf, (const void *)A,
+    rc = run_maybe_graph(std::make_tuple(1 + 16 * mode + (spec ? 0 : kNoSpecKey), n, lda, ldx, leaf, (const void *)A,
                                          (void *)Ainv, (void *)base, ns_steps),
                          s, body);
     if (rc || !rep) return rc;
 
-    // Report: residual of the unrefined and of the final inverse.
+    // Report: residual of the unrefined and of the final inverse.  With
+    // refinement the final residual and the norms of A and X come from the
+    // acceptance test above; X0 is no longer stored, so it is recomputed
+    // from X32.  Without refinement X0 is the result.
     std::memset(rep, 0, sizeof(*rep));
     rep->steps = ns_steps;
     double *misc = norms + kNormSlots;  // 0: |A|^2, 1: |X0|^2, 2: |R_final|^2, 3: |X|^2
-    hipError_t e = frob2(A, lda, n, n, parts, misc + 0, s);
-    // X0 is no longer stored once refinement ran: recompute it from X32.
-    double *x0 = (ns_steps > 0) ? R : Ainv;
-    int64_t ldx0 = (ns_steps > 0) ? n : ldx;
-    if (e == hipSuccess && ns_steps > 0) e = cast_f32_to_f64(X32, n, R, n, n, n, s);
-    if (e == hipSuccess) e = frob2(x0, ldx0, n, n, parts, misc + 1, s);
-    if (e == hipSuccess && ns_steps == 0) {
+    hipError_t e = hipSuccess;
+    if (ns_steps > 0) {
+        e = cast_f32_to_f64(X32, n, R, n, n, n, s);
+        if (e == hipSuccess) e = frob2(R, n, n, n, parts, misc + 1, s);
+    } else {
         GemmProb pr{A, Ainv, nullptr, R, lda, ldx, 1, n, (int32_t)n, (int32_t)n, (int32_t)n,
                     1, -1.0, 0.0};
         e = gemm_launch(&pr, 1, kF64, s, nullptr);
         if (e == hipSuccess) e = frob2(R, n, n, n, parts, norms + 0, s);
+        if (e == hipSuccess) e = frob2(R, n, n, n, parts, misc + 2, s);
+        if (e == hipSuccess) e = frob2(A, lda, n, n, parts, misc + 0, s);
+        if (e == hipSuccess) e = frob2(Ainv, ldx, n, n, parts, misc + 1, s);
+        if (e == hipSuccess) e = frob2(Ainv, ldx, n, n, parts, misc + 3, s);
     }
-    // final residual
-    if (e == hipSuccess) {
-        GemmProb pr{A, Ainv, nullptr, R, lda, ldx, 1, n, (int32_t)n, (int32_t)n, (int32_t)n,
-                    1, -1.0, 0.0};
-        e = gemm_launch(&pr, 1, kF64, s, nullptr);
-    }
-    if (e == hipSuccess) e = frob2(R, n, n, n, parts, misc + 2, s);
-    if (e == hipSuccess) e = frob2(Ainv, ldx, n, n, parts, misc + 3, s);
     // copies ordered on the caller's stream (not the null stream), then wait for it
     double h_norms[kNormSlots + 4];
     int h_status[2];
@@ -837,6 +896,37 @@ int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha, const vo
     LaunchInfo li{};
     if (g_trace_on) trace_cb(&ctx, li, 0);
     hipError_t e = gemm_launch(&pr, 1, dtype == SPIN_FP64 ? kF64 : mixed_product_type(dtype), s, &li);
+    if (g_trace_on) trace_cb(&ctx, li, 1);
+    return e == hipSuccess ? SPIN_OK : hip_fail(e);
+}
+
+int spin_gemm_int8(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda, const double *B,
+                   int64_t ldb, int epilogue, const double *C0, int64_t ldc, double *D, int64_t ldd,
+                   int moduli, int beta_a, int beta_b, spin_stream_t stream) {
+    if (epilogue < 0 || epilogue > 2 || moduli < 2 || moduli > kOzakiMaxModuli) return SPIN_E_MODE;
+    if (m < 0 || n < 0 || k < 0 || m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2)
+        return SPIN_E_N;
+    if (epilogue == 1 && m != n) return SPIN_E_N;
+    if (!D || (k > 0 && (!A || !B)) || (epilogue == 2 && !C0)) return SPIN_E_NULL;
+    if (ldd < std::max<int64_t>(m, 1) || (k > 0 && (lda < std::max<int64_t>(m, 1) ||
+                                                    ldb < std::max<int64_t>(k, 1))) ||
+        (epilogue == 2 && ldc < std::max<int64_t>(m, 1)))
+        return SPIN_E_LD;
+    if (beta_a <= 0 || beta_b <= 0) beta_a = beta_b = std::min(53, ozaki_beta(moduli, k));
+    if (beta_a < 1 || beta_b < 1 || beta_a > 53 || beta_b > 53 ||
+        1.0 + std::log2((double)std::max<int64_t>(k, 1)) + beta_a + beta_b >= ozaki_log2_modulus(moduli))
+        return SPIN_E_MODE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *w = nullptr;
+    int rc = ws_acquire(s, kHdr + ozaki_workspace_bytes(m, n, k, moduli), &w);
+    if (rc) return rc;
+    OzakiProb p{A, lda, B, ldb, C0, ldc, D, ldd, m, n, k, epilogue, moduli, beta_a, beta_b};
+    TraceCtx ctx{s, -1, nullptr};
+    LaunchInfo li{"gemm_int8_emulated", 2.0 * (double)m * (double)n * (double)k,
+                  8.0 * (double)(m * k + k * n + m * n)};
+    if (g_trace_on) trace_cb(&ctx, li, 0);
+    hipError_t e = ozaki_product(p, w->base + kHdr, s);
     if (g_trace_on) trace_cb(&ctx, li, 1);
     return e == hipSuccess ? SPIN_OK : hip_fail(e);
 }
@@ -885,9 +975,11 @@ int spin_residual(const double *A, int64_t n, int64_t lda, const double *X, int6
 
 size_t spin_workspace_bytes(int64_t n, int64_t leaf, int mode) {
     if (n < 1 || n > SPIN_MAX_N || leaf < 1 || leaf > SPIN_MAX_LEAF) return 0;
-    if (!is_mode(mode)) return 0;
-    Plan P = make_plan(n, n, n, leaf);
-    return layout_for(n, leaf, mode, P.ws_elems, P.max_leaf).total;
+    const bool sym = (mode & SPIN_SYMMETRIC) != 0;
+    const int pmode = mode & ~SPIN_SYMMETRIC;
+    if (!is_mode(pmode)) return 0;
+    Plan P = sym ? make_plan_spd(n, n, n, leaf) : make_plan(n, n, n, leaf);
+    return layout_for(n, leaf, pmode, P.ws_elems, P.max_leaf).total;
 }
 
 const char *spin_strerror(int code) {
@@ -902,7 +994,7 @@ const char *spin_strerror(int code) {
     case SPIN_E_COUNT: return "batch count out of range";
     case SPIN_E_NOMEM: return "device memory allocation failed";
     case SPIN_E_HIP: return "HIP runtime or kernel launch error";
-    case SPIN_NS_DIVERGED: return "Newton refinement residual did not decrease";
+    case SPIN_NS_DIVERGED: return "Newton refinement diverged or missed the residual bound";
     default: return code > 0 ? "zero or non-finite pivot in a leaf block" : "unknown status";
     }
 }

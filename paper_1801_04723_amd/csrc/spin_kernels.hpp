@@ -5,9 +5,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace spin {
+
+inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Element types.  kBF16 and kBF16X3 are product flavours on FP32 storage:
 // the operands are rounded to BF16 (X3: split into two BF16 terms) on their
@@ -95,11 +98,25 @@ hipError_t leaf_batch_launch(const LeafItem *items, int count, DType dt, hipStre
                              LaunchInfo *info);
 
 // Auxiliary kernels (aux.hip).
-// Status words start at INT_MAX ("no event"); kernels lower them atomically.
-hipError_t status_reset(int *status, int n_words, hipStream_t s);
+// Status words of an inversion: word 0 the pivot status and word 1 the
+// refinement status start at INT_MAX ("no event") and are lowered
+// atomically; word kStatusSpecWord is the leaves' speculation switch
+// (nonzero: try the speculative elimination first).
+constexpr int kStatusWords = 3;
+constexpr int kStatusSpecWord = 2;
+hipError_t status_reset(int *status, bool spec, hipStream_t s);
 // Value written to the refinement status word on divergence (SPIN_NS_DIVERGED).
 constexpr int kStatusNsDiverged = -100;
 hipError_t ns_check(const double *norms, int j, int *status, hipStream_t s);
+// Residual bound a refined inverse must meet: rho = |A X - I|_F / (|A|_F
+// |X|_F) <= kNsTol after the refinement steps, else the refinement status
+// word gets SPIN_NS_DIVERGED.
+constexpr double kNsTol = 1e-12;
+// Moduli of the refinement's INT8-emulated products (SPIN_REFINE_INT8): 14
+// give about 110 bits of modulus, operands of 47 bits at order 16384.
+constexpr int kRefineModuli = 14;
+hipError_t ns_final(const double *r2, const double *a2, const double *x2, double tol, int *status,
+                    hipStream_t s);
 hipError_t cast_f64_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t m,
                            int64_t n, hipStream_t s);
 hipError_t cast_f32_to_f64(const float *src, int64_t lds, double *dst, int64_t ldd, int64_t m,
@@ -120,6 +137,33 @@ hipError_t fill_zero_f64(double *d, int64_t ld, int64_t m, int64_t n, hipStream_
 constexpr int kLuLeafMax = 128;
 hipError_t lu_leaf_launch(const double *A, int64_t lda, double *Li, int64_t ldl, double *Ui,
                           int64_t ldu, int64_t L, int64_t col0, int *status, hipStream_t s);
+// FP64-accurate product on INT8 matrix cores (ozaki.hip): D = epilogue(A B)
+// with A (m x k, lda), B (k x n, ldb) column-major FP64; epilogue 0: D = A B,
+// 1: D = I - A B (m == n), 2: D = C0 + A B.  `moduli` residue products
+// (2 .. kOzakiMaxModuli); the operands are rounded to integers of at most
+// beta_a / beta_b bits per row / column, which must satisfy
+// 2 k 2^(beta_a + beta_b) < the product of the moduli (ozaki_beta gives the
+// largest equal pair).  ws: ozaki_workspace_bytes(m, n, k, moduli) bytes.
+constexpr int kOzakiMaxModuli = 15;
+struct OzakiProb {
+    const double *A;
+    int64_t lda;
+    const double *B;
+    int64_t ldb;
+    const double *C0;
+    int64_t ldc;
+    double *D;
+    int64_t ldd;
+    int64_t m, n, k;
+    int epilogue;
+    int moduli;
+    int beta_a, beta_b;
+};
+double ozaki_log2_modulus(int count);
+int ozaki_beta(int count, int64_t k);
+size_t ozaki_workspace_bytes(int64_t m, int64_t n, int64_t k, int count);
+hipError_t ozaki_product(const OzakiProb &p, void *ws, hipStream_t s);
+
 // Sum of squares of an (m x n) FP64 view, deterministic two-pass reduction:
 // partials (>= frob_partials_count(m, n) doubles) then one block writes *out.
 int frob_partials_count(int64_t m, int64_t n);

@@ -6,6 +6,8 @@
 #include <cstdint>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "spin.h"
 #include "spin_kernels.hpp"
 
@@ -60,7 +62,6 @@ struct Plan {
 //   then              recursion workspace, leaf scratch, mixed-mode buffers
 constexpr size_t kHdr = 4096 + 8192 + 4096;
 constexpr int kNormSlots = 8;
-inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Precision modes of the C ABI.
 inline bool is_mixed_mode(int mode) {
@@ -97,6 +98,10 @@ bool plan_folds_all(const Plan &P);
 // size es (8: FP64, 4: FP32 storage): sets pr[0].DT / lddt and returns true
 // when ops[i + 1] is taken over.
 bool fold_next_step(const Plan &P, size_t i, char *const base[3], size_t es, GemmProb pr[2]);
+
+// Whether leaves try the speculative elimination first (environment
+// variable SPIN_NO_SPEC unset or 0).
+bool leaf_spec_enabled();
 
 // Order of the leading block when an order-m block is split.
 int64_t split_order(int64_t m);

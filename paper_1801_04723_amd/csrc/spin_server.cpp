@@ -82,7 +82,7 @@ class PoolAllocator {
 
 // --------------------------------------------------------------- steps ----
 enum StepKind { STEP_GEMM = 0, STEP_LEAF = 1, STEP_AUX = 2 };
-enum AuxOp { AUX_RESET, AUX_CAST_IN, AUX_WIDEN, AUX_FROB, AUX_NSCHECK, AUX_TRANSPOSE, AUX_MIRROR };
+enum AuxOp { AUX_RESET, AUX_CAST_IN, AUX_WIDEN, AUX_FROB, AUX_NSCHECK, AUX_TRANSPOSE, AUX_MIRROR, AUX_NSFINAL };
 
 // A mode with SPIN_SYMMETRIC runs the symmetric schedule of spin_invert_spd
 // with the mode's product flavour.
@@ -239,12 +239,36 @@ bool build_steps(Request &r, int64_t leaf, int ns_steps) {
                              0, 1.0, 1.0};
         r.steps.push_back(u);
     }
+    if (ns_steps > 0) {
+        // acceptance of the refined inverse (now in X), as in spin_invert_mixed
+        double *misc = norms + kNormSlots;
+        Step g;
+        std::memset(&g, 0, sizeof(g));
+        g.kind = STEP_GEMM;
+        g.dt = kF64;
+        g.nprob = 1;
+        g.prob[0] = GemmProb{r.A, r.X, nullptr, R, r.lda, r.ldx, 1, n, (int32_t)n, (int32_t)n,
+                             (int32_t)n, 1, -1.0, 0.0};
+        r.steps.push_back(g);
+        const double *src[3] = {R, r.A, r.X};
+        const int64_t ld[3] = {n, r.lda, r.ldx};
+        const int slot[3] = {2, 0, 3};
+        for (int q = 0; q < 3; ++q) {
+            Step fr = aux_step(AUX_FROB);
+            fr.src = src[q], fr.lds = ld[q], fr.m = n, fr.n = n, fr.norms = misc + slot[q];
+            fr.partials = parts;
+            r.steps.push_back(fr);
+        }
+        Step fin = aux_step(AUX_NSFINAL);
+        fin.norms = misc, fin.status = status + 1;
+        r.steps.push_back(fin);
+    }
     return true;
 }
 
 hipError_t run_aux(const Step &s, hipStream_t st) {
     switch (s.aux) {
-    case AUX_RESET: return status_reset(s.status, 2, st);
+    case AUX_RESET: return status_reset(s.status, leaf_spec_enabled(), st);
     case AUX_CAST_IN:
         return cast_f64_to_f32(static_cast<const double *>(s.src), s.lds, static_cast<float *>(s.dst),
                                s.ldd, s.m, s.n, st);
@@ -254,6 +278,7 @@ hipError_t run_aux(const Step &s, hipStream_t st) {
     case AUX_FROB:
         return frob2(static_cast<const double *>(s.src), s.lds, s.m, s.n, s.partials, s.norms, st);
     case AUX_NSCHECK: return ns_check(s.norms, s.j, s.status, st);
+    case AUX_NSFINAL: return ns_final(s.norms + 2, s.norms + 0, s.norms + 3, kNsTol, s.status, st);
     case AUX_TRANSPOSE:
         return transpose_f64(static_cast<const double *>(s.src), s.lds, static_cast<double *>(s.dst),
                              s.ldd, s.m, s.n, st);

@@ -20,7 +20,7 @@ import collections
 import math
 import time
 
-from . import FP64, MIXED_FP32, SYMMETRIC, Server, server_request_bytes
+from . import FP64, MIXED_FP32, SYMMETRIC, Server, residual, server_request_bytes
 
 KAPPA_BUCKETS = (10 ** 1.5, 10 ** 2.5, 10 ** 3.5)
 
@@ -61,7 +61,7 @@ def percentile(xs, p):
 
 def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 << 30,
               max_active: int = 64, max_ticks_in_flight: int = 64, pool: MatrixPool | None = None,
-              split_n=None, symmetric: bool = False):
+              split_n=None, symmetric: bool = False, check_every: int = 25):
     """Serves `trace` (list of dicts with t, n, kind, kappa, mixed) and returns
     latency / throughput statistics.
 
@@ -75,7 +75,13 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
     the symmetric schedule (mode FP64 | SYMMETRIC), about half the flops.
     Mixed requests keep the plain schedule: their FP64 refinement dominates,
     so the symmetric one saves only a few percent there and leaves a larger
-    residual after the same number of Newton steps."""
+    residual after the same number of Newton steps.
+
+    check_every: every check_every-th request (by arrival) keeps its result;
+    after the run their residuals rho = |A X - I|_F / (|A|_F |X|_F) are
+    computed on the GPU (spin_residual) and reported, split by mode.  Mixed
+    requests are also checked by the library itself (rho <= 1e-12, else a
+    refinement-divergence status)."""
     import torch
     pool = pool or MatrixPool()
     # materialise the inputs before the clock starts
@@ -91,7 +97,7 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
                  for _ in range(len(bounds) + 1)]
     inflight = [collections.deque() for _ in lanes]
     lat, flops, statuses = [], 0.0, collections.Counter()
-    outs = {}
+    outs, kept = {}, {}
     nxt = 0
     done = 0
     t0 = time.perf_counter()
@@ -130,11 +136,22 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
                 lat.append(t_done - trace[tag]["t"])
                 flops += 2.0 * trace[tag]["n"] ** 3
                 statuses[info] += 1
-                outs.pop(tag, None)
+                x = outs.pop(tag, None)
+                if check_every and tag % check_every == 0:
+                    kept[tag] = (x, info)
                 done += 1
     makespan = time.perf_counter() - t0
     for srv, _ in lanes:
         srv.close()
+    checked = {"fp64": [], "mixed": []}
+    for tag, (x, info) in sorted(kept.items()):
+        r = trace[tag]
+        a = pool.get(r["n"], r["kind"], r["kappa"])
+        checked["mixed" if r["mixed"] else "fp64"].append((residual(a, x), info))
+    check = {k: {"count": len(v), "max_rho": max((rho for rho, _ in v), default=None),
+                 "above_1e-12": sum(1 for rho, _ in v if not rho <= 1e-12),
+                 "nonzero_status": sum(1 for _, info in v if info != 0)}
+             for k, v in checked.items()}
     return {
         "requests": len(trace),
         "p50_ms": 1e3 * percentile(lat, 50),
@@ -151,4 +168,5 @@ def run_trace(trace, leaf: int = 128, ns_steps: int = 2, pool_bytes: int = 32 <<
         "lanes": len(lanes),
         "split_n": bounds,
         "symmetric": bool(symmetric),
+        "residual_check": dict(check, every=check_every),
     }

@@ -116,9 +116,14 @@ def test_serving_loop_short_trace(torch_cuda, split, sym):
     import workloads as W
     trace = W.serving_trace(rate=100.0, duration=0.5, seed=11, n_max=512)
     stats = serve.run_trace(trace, leaf=64, ns_steps=2, pool_bytes=4 << 30, max_active=16,
-                            split_n=split, symmetric=sym)
+                            split_n=split, symmetric=sym, check_every=3)
     assert stats["symmetric"] == sym
     assert stats["requests"] == len(trace) > 10
     assert stats["status_counts"] == {0: len(trace)}
+    # every sampled result meets the residual target
+    chk = stats["residual_check"]
+    assert chk["mixed"]["count"] + chk["fp64"]["count"] >= len(trace) // 25
+    for k in ("mixed", "fp64"):
+        assert chk[k]["above_1e-12"] == 0 and chk[k]["nonzero_status"] == 0, chk
     assert stats["p50_ms"] <= stats["p99_ms"] <= stats["max_ms"]
     assert stats["lanes"] == (1 if split is None else 3)

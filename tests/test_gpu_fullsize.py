@@ -39,9 +39,9 @@ def _column_residual(torch, A, X, cols):
     return float((R.norm(dim=0) / (A.norm() * Xs.norm(dim=0))).max())
 
 
-@pytest.mark.parametrize("leaf", [128, 2048])
-def test_diag_dominant_16384_leaf_ends(torch_cuda, leaf):
-    """Leaf sweep end points: U(-1, 1) + n I, n = 16384, leaf 128 and 2048."""
+@pytest.mark.parametrize("leaf", [128, 256, 512, 1024, 2048])
+def test_diag_dominant_16384_leaf_sweep(torch_cuda, leaf):
+    """Every point of the leaf sweep: U(-1, 1) + n I, n = 16384, leaf 128 ... 2048."""
     import paper_1801_04723_amd as S
     torch = torch_cuda
     A = W.torch_diag_dominant(N, seed=16384 + leaf)

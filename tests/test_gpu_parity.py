@@ -121,7 +121,7 @@ def test_gemm_f32_parity(torch_cuda, m, n, k):
 
 
 # ------------------------------------------------------------------- leaves
-LEAF_SIZES = [1, 2, 3, 16, 17, 31, 64, 100, 128, 129, 200, 256, 300, 512, 777, 1024]
+LEAF_SIZES = [1, 2, 3, 16, 17, 31, 64, 100, 128, 129, 200, 256, 300, 512, 777, 1024, 1536, 2048]
 
 
 @pytest.mark.parametrize("L", LEAF_SIZES)
@@ -295,6 +295,23 @@ def test_golden_unimodular_exact(torch_cuda):
     assert np.array_equal(X, ref)
 
 
+def test_status_survives_a_growing_residual_call(torch_cuda):
+    """spin_residual may grow the stream's workspace; the status words of the
+    inversion before it move along, so spin_info still reports it."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    S.release()
+    n, leaf = 256, 128
+    A = W.diag_dominant(n, seed=2)
+    A[:, 100] = 0.0
+    A[100, :] = 0.0
+    dA = _dev_f(torch, A)
+    dX = S.invert(dA, leaf=leaf)
+    assert S.workspace_bytes(n, leaf) < 16384 + 8 * n * n  # the residual needs more
+    S.residual(dA, dX)
+    assert S.info() == 101
+
+
 def test_singular_leaf_reports_column(torch_cuda):
     import paper_1801_04723_amd as S
     torch = torch_cuda
@@ -386,6 +403,41 @@ def test_full_size_spd_sampled(torch_cuda, n, leaf):
     ref = np.linalg.solve(A, E)
     assert np.linalg.norm(Xs - ref) / np.linalg.norm(ref) <= 1e-12
     assert np.linalg.norm(A @ Xs - E) / np.linalg.norm(E) <= 1e-12
+
+
+def _lambda_max_power(A, iters=60, seed=0):
+    """Largest eigenvalue of a symmetric positive-definite A by power iteration
+    (an upper estimate once converged: the Rayleigh quotient of the last iterate)."""
+    v = np.random.default_rng(seed).standard_normal(A.shape[0])
+    for _ in range(iters):
+        v = A @ v
+        v /= np.linalg.norm(v)
+    return float(v @ (A @ v))
+
+
+@pytest.mark.parametrize("n,leaf", [(8192, 256)])
+def test_full_size_spd_against_oracle(torch_cuda, n, leaf):
+    """The benchmark configuration against the oracle's recursion (O2) on the
+    same matrix: forward error <= max(1e-13, 100 kappa u), and every element
+    within 100 kappa u of its column's largest oracle entry.  A = B B^T / n + I
+    has smallest eigenvalue >= 1, so kappa <= lambda_max (power iteration,
+    with 5 % slack)."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    A = W.spd_gram(n, seed=2)
+    dA = _dev_f(torch, A)
+    X = _host(S.invert(dA, leaf=leaf))
+    assert S.info() == 0
+    ref, info = oracle.strassen_inv(A, leaf)
+    assert info == 0
+    kap = 1.05 * _lambda_max_power(A)
+    assert 1.0 < kap < 10.0, kap
+    tol = max(1e-13, 100 * kap * U)
+    err = np.linalg.norm(X - ref) / np.linalg.norm(ref)
+    assert err <= tol, (err, tol)
+    colmax = np.abs(ref).max(axis=0)
+    elem = (np.abs(X - ref).max(axis=0) / colmax).max()
+    assert elem <= 100 * kap * U, elem
 
 
 def test_graph_cache_stays_bounded_and_correct(torch_cuda):

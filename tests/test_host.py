@@ -126,6 +126,17 @@ def test_workspace_bound(n, leaf):
     assert S.workspace_bytes(n, leaf, "fp32") >= 4 * ws + 24 * n * n
 
 
+@pytest.mark.parametrize("n,leaf", [(256, 64), (1024, 128), (8192, 256), (300, 64), (100, 7)])
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "bf16x3"])
+def test_workspace_bytes_symmetric(n, leaf, mode):
+    """The symmetric schedule's workspace (mode | SPIN_SYMMETRIC) is sized from
+    its own plan: nonzero, and no larger than the plain schedule's."""
+    plain = S.workspace_bytes(n, leaf, mode)
+    sym = S.workspace_bytes(n, leaf, S.MODES[mode] | S.SYMMETRIC)
+    assert 0 < sym <= plain
+    assert S.workspace_bytes(n, leaf, 7 | S.SYMMETRIC) == 0
+
+
 @pytest.mark.parametrize("m", list(range(1, 300, 7)) + [4096, 4160, 8191, 16384])
 def test_split_rule_matches_oracle(m):
     if m == 1:
