@@ -61,6 +61,8 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
 #define SPIN_E_ALIAS (-5)     /* A and Ainv overlap                            */
 #define SPIN_E_MODE (-6)      /* unknown precision mode or refinement count    */
 #define SPIN_E_COUNT (-7)     /* batch count < 0 or above SPIN_MAX_BATCH       */
+#define SPIN_E_SCRATCH (-8)   /* spin_invert_noalloc: the order needs more
+                                 workspace than its fixed scratch holds        */
 #define SPIN_E_NOMEM (-10)    /* device allocation of the workspace failed     */
 #define SPIN_E_HIP (-11)      /* a HIP runtime call or kernel launch failed    */
 /* numerical status (positive values come from spin_info / info arrays):      */
@@ -111,6 +113,29 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
  * leaf that meets a zero pivot column reports it through spin_info(). */
 int spin_invert(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
                 int64_t leaf, spin_stream_t stream);
+
+/* ---- FP64 inversion without allocation ------------------------------------ */
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops that forbid allocation): the inversion of spin_invert, with
+ * the same arguments, kernels, schedule and result bit for bit, whose
+ * workspace is a fixed device array of SPIN_NOALLOC_SCRATCH_MB MiB that the
+ * library holds on each GPU it runs on until the process ends.  The call
+ * makes no device allocation, captures no graph and launches its kernels
+ * directly on `stream`.
+ *   Limit      the order and leaf must fit the array: spin_workspace_bytes(n,
+ *              leaf, SPIN_FP64) <= SPIN_NOALLOC_SCRATCH_MB MiB (about n <= 2800);
+ *              larger requests return SPIN_E_SCRATCH and enqueue nothing.
+ *   Status     written by the GPU to the device int *info (0, or the 1-based
+ *              column of a failing leaf pivot) after the work completes, in
+ *              stream order; info may be NULL.  spin_info() does not cover
+ *              this call.
+ *   Sharing    every call on one GPU uses that GPU's one array, whatever the
+ *              stream: calls that overlap in time on one GPU race and give
+ *              unspecified results; order them (one stream, or events).
+ * Other arguments and errors as for spin_invert. */
+#define SPIN_NOALLOC_SCRATCH_MB 64
+int spin_invert_noalloc(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                        int64_t leaf, int *info, spin_stream_t stream);
 
 /* ---- FP64 inversion through a block LU factorisation ---------------------- */
 /* Ainv := A^-1 by the method the paper compares SPIN with (Sec. 5, after Liu

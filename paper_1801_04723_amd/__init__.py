@@ -140,6 +140,8 @@ def lib() -> ctypes.CDLL:
         L.spin_plan_describe_lu.restype = _i64
         L.spin_plan_ws_elems_lu.argtypes = [_i64, _i64]
         L.spin_plan_ws_elems_lu.restype = _i64
+        L.spin_invert_noalloc.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _vp, _vp]
+        L.spin_invert_noalloc.restype = ctypes.c_int
         L.spin_invert_lu.argtypes = L.spin_invert.argtypes
         L.spin_invert_lu.restype = ctypes.c_int
         L.spin_invert_spd.argtypes = L.spin_invert.argtypes
@@ -307,6 +309,28 @@ def invert(a, leaf: int, out=None, stream=None):
     rc = lib().spin_invert(a.data_ptr(), a.shape[0], lda, out.data_ptr(), ldx, int(leaf), _stream(stream))
     if rc != 0:
         raise SpinError(rc, "spin_invert")
+    return out
+
+
+NOALLOC_SCRATCH_MB = 64  # SPIN_NOALLOC_SCRATCH_MB
+
+
+def invert_noalloc(a, leaf: int, out, info=None, stream=None):
+    """spin_invert_noalloc: spin_invert on the library's fixed scratch, with
+    no device allocation by the library.  `out` (same layout as `a`) and the
+    optional one-element int32 device tensor `info` are the caller's; the
+    status lands in `info` in stream order.  Returns `out`."""
+    _check_square(a)
+    lda, order = _layout(a)
+    ldx, order_x = _layout(out)
+    if order != order_x:
+        raise ValueError("output must have the same memory order as the input")
+    if info is not None and (info.dtype.itemsize != 4 or info.numel() < 1):
+        raise ValueError("info must hold at least one 32-bit integer")
+    rc = lib().spin_invert_noalloc(a.data_ptr(), a.shape[0], lda, out.data_ptr(), ldx, int(leaf),
+                                   None if info is None else info.data_ptr(), _stream(stream))
+    if rc != 0:
+        raise SpinError(rc, "spin_invert_noalloc")
     return out
 
 

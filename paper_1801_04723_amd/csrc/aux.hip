@@ -16,6 +16,10 @@ __global__ void k_status_reset(int *status, int spec) {
     if (i < kStatusWords) status[i] = (i == kStatusSpecWord && !spec) ? 0 : INT_MAX;
 }
 
+__global__ void k_status_copy(const int *status, int *info) {
+    if (threadIdx.x == 0) info[0] = status[0] == INT_MAX ? 0 : status[0];
+}
+
 // 2-D grid-stride conversion of an (m x n) column-major view.
 template <typename S, typename D>
 __global__ void __launch_bounds__(256)
@@ -147,6 +151,11 @@ hipError_t convert(const S *src, int64_t lds, D *dst, int64_t ldd, int64_t m, in
 
 hipError_t status_reset(int *status, bool spec, hipStream_t s) {
     hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, s, status, spec ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t status_copy(const int *status, int *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_copy, dim3(1), dim3(64), 0, s, status, info);
     return hipGetLastError();
 }
 

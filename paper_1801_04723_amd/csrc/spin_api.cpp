@@ -498,6 +498,7 @@ struct Exec {
     int *status;
     void *leaf_scratch;
     DType gdt = kF64;  // product flavour of the plan's products
+    bool no_trace = false;  // never trace (the allocation-free entry point)
 };
 
 inline void *at(const Exec &E, const Ref &r) {
@@ -508,7 +509,7 @@ hipError_t run_plan(const Plan &P, const Exec &E) {
     for (size_t i = 0; i < P.ops.size(); ++i) {
         const POp &op = P.ops[i];
         TraceCtx ctx{E.s, op.level, nullptr};
-        const bool tr = g_trace_on;
+        const bool tr = g_trace_on && !E.no_trace;
         if (op.kind == 0) {
             GemmProb pr[2];
             for (int q = 0; q < op.count; ++q) pr[q] = make_prob(E.base, E.es, op.g[q]);
@@ -643,6 +644,31 @@ double *norm_ptr(Workspace *w) { return reinterpret_cast<double *>(w->base + 256
 double *partials_ptr(Workspace *w) { return reinterpret_cast<double *>(w->base + 4096); }
 
 }  // namespace
+}  // namespace spin
+
+namespace spin {
+
+size_t invert_workspace_bytes(int64_t n, int64_t leaf) {
+    const Plan P = make_plan(n, n, n, leaf);
+    return layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf).total;
+}
+
+int invert_on_workspace(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                        int64_t leaf, char *ws, size_t ws_bytes, int *info, hipStream_t s) {
+    int rc = validate(A, n, lda, Ainv, ldx, leaf);
+    if (rc) return rc;
+    const Plan P = make_plan(n, lda, ldx, leaf);
+    const Layout L = layout_for(n, leaf, SPIN_FP64, P.ws_elems, P.max_leaf);
+    if (L.total > ws_bytes) return SPIN_E_SCRATCH;
+    Exec E{s, {(char *)A, (char *)Ainv, ws + L.rec_off}, 8, kF64, reinterpret_cast<int *>(ws),
+           ws + L.leaf_off};
+    E.no_trace = true;
+    hipError_t e = status_reset(E.status, leaf_spec_enabled(), s);
+    if (e == hipSuccess) e = run_plan(P, E);
+    if (e == hipSuccess && info) e = status_copy(E.status, info, s);
+    return e == hipSuccess ? SPIN_OK : hip_fail(e);
+}
+
 }  // namespace spin
 
 using namespace spin;
@@ -992,6 +1018,7 @@ const char *spin_strerror(int code) {
     case SPIN_E_ALIAS: return "input and output overlap";
     case SPIN_E_MODE: return "unknown precision mode or refinement step count";
     case SPIN_E_COUNT: return "batch count out of range";
+    case SPIN_E_SCRATCH: return "order too large for the fixed scratch of spin_invert_noalloc";
     case SPIN_E_NOMEM: return "device memory allocation failed";
     case SPIN_E_HIP: return "HIP runtime or kernel launch error";
     case SPIN_NS_DIVERGED: return "Newton refinement diverged or missed the residual bound";

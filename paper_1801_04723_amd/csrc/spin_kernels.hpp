@@ -105,6 +105,8 @@ hipError_t leaf_batch_launch(const LeafItem *items, int count, DType dt, hipStre
 constexpr int kStatusWords = 3;
 constexpr int kStatusSpecWord = 2;
 hipError_t status_reset(int *status, bool spec, hipStream_t s);
+// *info = the pivot status word (0 when it holds "no event"), by a kernel.
+hipError_t status_copy(const int *status, int *info, hipStream_t s);
 // Value written to the refinement status word on divergence (SPIN_NS_DIVERGED).
 constexpr int kStatusNsDiverged = -100;
 hipError_t ns_check(const double *norms, int j, int *status, hipStream_t s);

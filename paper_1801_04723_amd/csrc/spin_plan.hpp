@@ -103,6 +103,14 @@ bool fold_next_step(const Plan &P, size_t i, char *const base[3], size_t es, Gem
 // variable SPIN_NO_SPEC unset or 0).
 bool leaf_spec_enabled();
 
+// Bytes of workspace the FP64 schedule of an order-n inversion needs, and
+// that inversion on a caller-provided workspace: launched eagerly on s (no
+// graph, no trace, no allocation); its numerical status (0 or the 1-based
+// failing pivot column) is copied to the device int *info when info is set.
+size_t invert_workspace_bytes(int64_t n, int64_t leaf);
+int invert_on_workspace(const double *A, int64_t n, int64_t lda, double *Ainv, int64_t ldx,
+                        int64_t leaf, char *ws, size_t ws_bytes, int *info, hipStream_t s);
+
 // Order of the leading block when an order-m block is split.
 int64_t split_order(int64_t m);
 // Depth-first S-form schedule of Alg. 1 for an order-n matrix.
