@@ -67,7 +67,8 @@ def parse():
     p.add_argument("--mixed-leaf", type=int, default=256)
     p.add_argument("--mixed-reps", type=int, default=2)
     p.add_argument("--gemm-sweep", action="store_true",
-                   help="only time spin_gemm alone (FP64, FP32, BF16, bf16x3; h = 2048, 4096, 8192) and exit")
+                   help="only time spin_gemm alone (FP64, FP32, BF16, bf16x3) and spin_gemm_int8 "
+                        "(FP64-accurate on INT8 cores), h = 2048, 4096, 8192, and exit")
     p.add_argument("--lu-compare", action="store_true",
                    help="only time Alg. 1 against inversion through a block LU factorisation "
                         "(U(-1,1) + n I, n = 8192 and 16384, leaf 128) and exit")
@@ -226,7 +227,7 @@ def mixed_vs_fp64(n: int, leaf: int, reps: int):
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     dX = torch.empty_like(dA)
-    runs = [("fp64", 0), ("fp32", 2), ("bf16x3", 3), ("bf16", 2)]
+    runs = [("fp64", 0), ("fp32", 2), ("bf16x3", 3), ("bf16", 2), ("fp32_int8", 2), ("bf16x3_int8", 3)]
     out = {"workload": f"spd_spectrum (Q diag(lam) Q^T, kappa 1e4) n={n} generated on the GPU "
                        f"(seed 4, {gen_s:.1f} s), leaf {leaf}",
            "n": n, "leaf": leaf, "modes": {}}
@@ -417,13 +418,17 @@ def gemm_sweep():
     rows = []
     for h in (2048, 4096, 8192):
         for mode, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16", torch.float32),
-                         ("bf16x3", torch.float32)):
+                         ("bf16x3", torch.float32), ("int8emu", torch.float64)):
             g = torch.Generator(device="cuda")
             g.manual_seed(h)
             a = torch.rand(h, h, dtype=dt, device="cuda", generator=g)
             b = torch.rand(h, h, dtype=dt, device="cuda", generator=g)
             d = torch.empty(h, h, dtype=dt, device="cuda")
-            call = lambda: spin.gemm_cm(h, h, h, 1.0, a, h, b, h, 0.0, None, h, d, h, False, mode)  # noqa: E731
+            if mode == "int8emu":
+                # FP64-accurate product on INT8 matrix cores, 14 moduli
+                call = lambda: spin.gemm_int8(h, h, h, a, h, b, h, 0, None, 1, d, h)  # noqa: E731
+            else:
+                call = lambda: spin.gemm_cm(h, h, h, 1.0, a, h, b, h, 0.0, None, h, d, h, False, mode)  # noqa: E731
             for _ in range(3):
                 call()
             torch.cuda.synchronize()
