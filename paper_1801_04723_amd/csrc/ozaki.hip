@@ -47,6 +47,7 @@ struct ModArgs {
     unsigned long long w_lo[kOzakiMaxModuli], w_hi[kOzakiMaxModuli];  // CRT weights
     unsigned long long M_lo, M_hi;        // product of the moduli
     double invM;                          // 1 / M (approximate)
+    int every;                            // terms summed between reductions mod M
 };
 
 constexpr unsigned long long kNonFinite = 0x7ff0000000000000ull;  // |x| bits at or above: Inf / NaN
@@ -267,6 +268,85 @@ __global__ void __launch_bounds__(256, 2) k_gemm_i8(const int8_t *__restrict__ a
         }
 }
 
+// The same product with 256 x 256 tiles: eight waves, each 128 x 64 (8 x 4
+// blocks), twice the integer operations per byte of residues moved, for the
+// large products of the refinement.  Residue planes padded to 256 rows.
+constexpr int kTB2 = 256;
+
+__global__ void __launch_bounds__(512, 1) k_gemm_i8_256(const int8_t *__restrict__ ap,
+                                                         const int8_t *__restrict__ bp,
+                                                         uint8_t *__restrict__ cp, int m, int n,
+                                                         int64_t mp, int64_t np_, int kp, ModArgs md) {
+    __shared__ __attribute__((aligned(16))) int8_t As[2][kTB2 * kPitch];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][kTB2 * kPitch];
+    const int l = blockIdx.z;
+    const int i0 = blockIdx.x * kTB2, j0 = blockIdx.y * kTB2;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = (w & 1) * 128, wn = (w >> 1) * 64;
+    const int8_t *A = ap + (int64_t)l * mp * kp + (int64_t)i0 * kp;
+    const int8_t *B = bp + (int64_t)l * np_ * kp + (int64_t)j0 * kp;
+    // slab loads: 1024 pieces of 16 bytes per operand, two per thread
+    const int r0 = t >> 2, r1 = (t + 512) >> 2, pc = (t & 3) * 16;
+    v4i ra0, ra1, rb0, rb1;
+    auto load = [&](int q0) {
+        ra0 = *reinterpret_cast<const v4i *>(A + (int64_t)r0 * kp + q0 + pc);
+        ra1 = *reinterpret_cast<const v4i *>(A + (int64_t)r1 * kp + q0 + pc);
+        rb0 = *reinterpret_cast<const v4i *>(B + (int64_t)r0 * kp + q0 + pc);
+        rb1 = *reinterpret_cast<const v4i *>(B + (int64_t)r1 * kp + q0 + pc);
+    };
+    auto store = [&](int buf) {
+        *reinterpret_cast<v4i *>(&As[buf][r0 * kPitch + pc]) = ra0;
+        *reinterpret_cast<v4i *>(&As[buf][r1 * kPitch + pc]) = ra1;
+        *reinterpret_cast<v4i *>(&Bs[buf][r0 * kPitch + pc]) = rb0;
+        *reinterpret_cast<v4i *>(&Bs[buf][r1 * kPitch + pc]) = rb1;
+    };
+    v4i acc[8][4];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+    const int nk = kp / kSK;
+    load(0);
+    store(0);
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 16;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) load((kt + 1) * kSK);
+        v4i fb[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            fb[b] = *reinterpret_cast<const v4i *>(&Bs[buf][(wn + 16 * b + fr) * kPitch + fk]);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const v4i fa = *reinterpret_cast<const v4i *>(&As[buf][(wm + 16 * a + fr) * kPitch + fk]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa, fb[b], acc[a][b], 0, 0, 0);
+        }
+        if (kt + 1 < nk) store(buf ^ 1);
+        __syncthreads();
+    }
+    const int mod = md.m[l];
+    uint8_t *C = cp + (int64_t)l * mp * np_;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = i0 + wm + 16 * a + 4 * (lane >> 4);
+            const int j = j0 + wn + 16 * b + (lane & 15);
+            if (j >= n || i >= m) continue;
+            unsigned int packed = 0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int r = acc[a][b][v] % mod;
+                if (r < 0) r += mod;
+                packed |= (unsigned int)r << (8 * v);
+            }
+            *reinterpret_cast<unsigned int *>(C + i + (int64_t)j * mp) = packed;
+        }
+}
+
 // ------------------------------------------------------- reconstruction ---
 __device__ inline u128 mk128(unsigned long long lo, unsigned long long hi) {
     return ((u128)hi << 64) | lo;
@@ -298,14 +378,18 @@ __global__ void __launch_bounds__(256) k_crt(const uint8_t *__restrict__ cp, int
     const int64_t total = (int64_t)m * n;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
         const int i = (int)(e % m), j = (int)(e / m);
+        // sum of r_l w_l, reduced mod M after every `every` terms (the host
+        // picks `every` so that the partial sum stays below 2^127)
         u128 S = 0;
         for (int l = 0; l < md.count; ++l) {
             const unsigned int r = cp[(int64_t)l * mp * np_ + i + (int64_t)j * mp];
-            S += (u128)r * mk128(md.w_lo[l], md.w_hi[l]);  // < M + 2^8 M
-            unsigned long long q = (unsigned long long)(u128_to_double(S) * md.invM);
-            if (q) S -= (u128)q * M;        // may step below zero by one M
-            if ((S >> 127) != 0) S += M;    // wrapped: the estimate was one too high
-            if (S >= M) S -= M;
+            S += (u128)r * mk128(md.w_lo[l], md.w_hi[l]);
+            if ((l + 1) % md.every == 0 || l + 1 == md.count) {
+                unsigned long long q = (unsigned long long)(u128_to_double(S) * md.invM);
+                if (q) S -= (u128)q * M;        // the estimate may be one too high or low
+                if ((S >> 127) != 0) S += M;    // wrapped below zero
+                if (S >= M) S -= M;
+            }
         }
         const bool neg = S > halfM;
         const u128 mag = neg ? M - S : S;
@@ -366,10 +450,18 @@ ModArgs make_moduli(int count) {
     md.M_lo = (unsigned long long)M;
     md.M_hi = (unsigned long long)(M >> 64);
     md.invM = 1.0 / ((double)md.M_hi * 18446744073709551616.0 + (double)md.M_lo);
+    // a partial sum below M plus `every` terms below 256 M each must stay
+    // below 2^127 (the top bit marks a wrap in the reduction)
+    const u128 lim = ((u128)1 << 127) / M;  // floor(2^127 / M)
+    md.every = (int)std::max<u128>(1, std::min<u128>((lim - 1) / 256, (u128)count));
     return md;
 }
 
 int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Tile of the INT8 product: 256 x 256 when both sides hold at least four
+// such tiles, else 128 x 128.
+int64_t tile_for(int64_t m, int64_t n) { return (m >= 4 * kTB2 && n >= 4 * kTB2) ? kTB2 : kTB; }
 }  // namespace
 
 double ozaki_log2_modulus(int count) {
@@ -384,7 +476,8 @@ int ozaki_beta(int count, int64_t k) {
 }
 
 size_t ozaki_workspace_bytes(int64_t m, int64_t n, int64_t k, int count) {
-    const int64_t mp = rup(m, kTB), np_ = rup(n, kTB), kp = rup(k > 0 ? k : 1, kSK);
+    const int64_t tile = tile_for(m, n);
+    const int64_t mp = rup(m, tile), np_ = rup(n, tile), kp = rup(k > 0 ? k : 1, kSK);
     size_t b = 0;
     b += al256((size_t)count * mp * kp);   // left residues
     b += al256((size_t)count * np_ * kp);  // right residues
@@ -398,7 +491,8 @@ hipError_t ozaki_product(const OzakiProb &p, void *ws, hipStream_t s) {
     if (p.moduli < 2 || p.moduli > kOzakiMaxModuli) return hipErrorInvalidValue;
     if (p.m <= 0 || p.n <= 0) return hipSuccess;
     const int64_t m = p.m, n = p.n, k = p.k;
-    const int64_t mp = rup(m, kTB), np_ = rup(n, kTB), kp = rup(k > 0 ? k : 1, kSK);
+    const int64_t tile = tile_for(m, n);
+    const int64_t mp = rup(m, tile), np_ = rup(n, tile), kp = rup(k > 0 ? k : 1, kSK);
     if (mp > INT_MAX / 2 || np_ > INT_MAX / 2 || kp > INT_MAX / 2) return hipErrorInvalidValue;
     const ModArgs md = make_moduli(p.moduli);
     char *w = static_cast<char *>(ws);
@@ -432,8 +526,12 @@ hipError_t ozaki_product(const OzakiProb &p, void *ws, hipStream_t s) {
     const int64_t cchunks = np_ * (kp / 16);
     hipLaunchKernelGGL(k_split_cols, dim3((unsigned)((cchunks + 255) / 256)), dim3(256), 0, s, p.B,
                        p.ldb, (int)k, (int)n, tb, bpl, np_, (int)kp, md);
-    hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)(mp / kTB), (unsigned)(np_ / kTB), (unsigned)p.moduli),
-                       dim3(256), 0, s, apl, bpl, cpl, (int)m, (int)n, mp, np_, (int)kp, md);
+    if (tile == kTB2)
+        hipLaunchKernelGGL(k_gemm_i8_256, dim3((unsigned)(mp / kTB2), (unsigned)(np_ / kTB2), (unsigned)p.moduli),
+                           dim3(512), 0, s, apl, bpl, cpl, (int)m, (int)n, mp, np_, (int)kp, md);
+    else
+        hipLaunchKernelGGL(k_gemm_i8, dim3((unsigned)(mp / kTB), (unsigned)(np_ / kTB), (unsigned)p.moduli),
+                           dim3(256), 0, s, apl, bpl, cpl, (int)m, (int)n, mp, np_, (int)kp, md);
     const int64_t total = m * n;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(k_crt, dim3((unsigned)blocks), dim3(256), 0, s, cpl, mp, np_, (int)m, (int)n, sa,

@@ -122,6 +122,30 @@ def test_integer_data_exact_and_nonfinite(torch_cuda):
     assert np.array_equal(got[mask], (np.nan_to_num(A) @ np.nan_to_num(B, posinf=0))[mask])
 
 
+@pytest.mark.parametrize("m,n,k,epi", [(1030, 1290, 333, 0), (1100, 1100, 700, 1), (1024, 1536, 64, 2),
+                                         (1023, 2049, 129, 0)])
+def test_large_tile_ragged_sampled_rows(torch_cuda, m, n, k, epi):
+    """Products with both sides of at least 1024 run on the 256 x 256 tile:
+    ragged edges in m, n and k, sampled rows (every tile boundary and the
+    last row) bit for bit against the definition."""
+    g = np.random.default_rng(m + 3 * n + 7 * k)
+    A = g.standard_normal((m, k)) * np.exp2(g.integers(-20, 20, size=(m, 1)))
+    B = g.standard_normal((k, n)) * np.exp2(g.integers(-20, 20, size=(1, n)))
+    C0 = g.standard_normal((m, n)) if epi == 2 else None
+    got = _run(torch_cuda, A, B, epi, C0, pad=1)
+    rows = np.unique(np.concatenate([[0, 127, 128, 255, 256, 511, 512, m - 1],
+                                     g.choice(m, 4, replace=False)]))
+    beta = min(53, OZ.beta_for(k, _log2M(14)))
+    D = OZ.emulated_product(A[rows], B, beta, beta)
+    if epi == 1:
+        want = np.eye(m, n)[rows] - D
+    elif epi == 2:
+        want = C0[rows] + D
+    else:
+        want = D
+    assert _same(got[rows], want)
+
+
 def test_full_size_sampled_rows(torch_cuda):
     """Order 4096, the refinement's residual shape: sampled rows bit for bit
     (a row's shift depends only on that row, a column's on that column)."""
