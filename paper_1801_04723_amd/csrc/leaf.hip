@@ -25,10 +25,15 @@
 //   (E = unit entries at the pivot rows) and the pivot rows Q of the other
 //   columns; those columns are then updated by one grouped matrix-core
 //   product  Z[:, out] += U' * Q.  A final pass writes the permuted result.
-//   Up to order 512 the panel kernel is the same 2-D kernel, and an FP64
-//   leaf is not copied first: the first panel and its product read the
-//   leaf's input in place.  Above 512 a rotating-slot panel kernel works on
-//   narrower panels and the input is copied into Z.
+//   Up to order 512 the panel's search kernel is the same 2-D kernel, its
+//   speculative elimination a column-block kernel, and an FP64 leaf is not
+//   copied first: the first panel and its product read the leaf's input in
+//   place.  Above 512 a rotating-slot panel kernel works on narrower panels
+//   and the input is copied into Z.
+//
+// Speculation: every kernel up to order 512 first tries the diagonal pivots,
+// checks each choice exactly and falls back to its search when a check fails
+// (gj2d_any); the result is the search's bit for bit either way.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -327,7 +332,7 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
     if (t == 0 && bad) atomicMin(a.status, a.col0 + k0 + bad);
 }
 
-// ------------------------------------------------ speculative 2-D kernel ---
+// ------------------------------------------ speculative whole-leaf kernel ---
 // The elimination of gj2d_run for blocks whose partial-pivoting choice at
 // step k is row k itself, as it is at every step for strictly diagonally
 // dominant blocks (their Schur complements stay dominant) and, in practice,
@@ -340,122 +345,66 @@ __device__ __attribute__((always_inline)) inline void gj2d_run(const LeafArgs &a
 //
 // With the pivot row known in advance the search leaves the dependent chain,
 // and so does one barrier: once step c is applied, the owners of column c+1
-// publish its multipliers and the owners of row c+1 the pivot row (whole
-// leaves: scaled, since the pivot row's wave also holds the pivot; panels:
-// raw, with the inverse pivot published by the pivot's owner), and after one
-// barrier every thread applies step c+1.  Every element goes through the
-// same operations as in gj2d_run (the same division, products and fused
-// multiply-adds), so when every check passes the outputs are gj2d_run's bit
-// for bit.  They are written only then.  Returns whether every check passed
-// (the same in every thread); on false nothing has been written.
-template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
+// publish its multipliers and the owners of row c+1 (one wave, which also
+// holds the pivot) the scaled pivot row, and after one barrier every thread
+// applies step c+1.  Every element goes through the same operations as in
+// gj2d_run (the same division, products and fused multiply-adds), so when
+// every check passes the outputs are gj2d_run's bit for bit.  They are written
+// only then.  Returns whether every check passed (the same in every thread);
+// on false nothing has been written.  Whole leaves only (panels have their
+// own kernels below).
+template <int TR, int RR, int RC, typename TI, typename TO>
 __device__ __attribute__((always_inline)) inline bool gj2d_spec(const LeafArgs &a) {
-    constexpr int NT = 16 * TR;
     constexpr int LMAX = TR * RR;
     constexpr int NBMAX = 16 * RC;
     static_assert(TR == 16 || TR == 32, "row groups of 16 or 32 threads");
     // Shared arrays are indexed by register slot, not by row: entry tr + TR r
     // belongs to slot r of the threads with that tr (the same map in every
     // thread), so that every access is a per-thread base plus a constant.
-    __shared__ double fbs[2][LMAX];   // multipliers of a step, -1 / 0 at its pivot row
-    __shared__ double rws[2][NBMAX];  // its pivot row (see above)
-    __shared__ double pvs[2][2];      // |pivot| (whole leaves) and 1 / pivot (panels)
+    __shared__ double fbs[2][LMAX];   // multipliers of a step, -1 at its pivot row
+    __shared__ double rws[2][NBMAX];  // its scaled pivot row
+    __shared__ double pvs[2];         // |pivot|
     const int t = threadIdx.x, wave = t >> 6;
-    const int tr = WHOLE ? t >> 4 : t % TR, tc = WHOLE ? t & 15 : t / TR;
+    const int tr = t >> 4, tc = t & 15;
     const int L = a.L;
-    const int k0 = WHOLE ? 0 : a.k0;
-    const int nb = WHOLE ? a.L : a.nb;
-    const double *src = WHOLE ? nullptr : (a.in ? static_cast<const double *>(a.in) : a.Z);
-    const int64_t lds = WHOLE ? 0 : (a.in ? a.ldi : a.ldz);
-    // Register slot r holds row tr + TR ((r + rot) mod RR), rot = k0 / TR: the
-    // row map turns with the panel's first column (a multiple of TR), so that
-    // the pivot row of step c (row k0 + c) sits in slot c / TR of thread
-    // c mod TR, a constant of the unrolled column block cb = c / 16.  Slots
-    // r >= RR - rot hold the rows before the panel, all of them used.
-    const int rot = k0 / TR;
-    int rowr[RR];
-#pragma unroll
-    for (int r = 0; r < RR; ++r) rowr[r] = tr + TR * ((r + rot) % RR);
 
     double z[RR][RC];
-    bool viol = !WHOLE && (k0 % TR) != 0;
 #pragma unroll
-    for (int r = 0; r < RR; ++r) {
-        const int row = rowr[r];
-        // the rows before the panel must be the used ones and no other
-        if (!WHOLE && k0 > 0 && row < L && ((a.used[row] != 0) != (row < k0))) viol = true;
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
         for (int q = 0; q < RC; ++q) {
-            const int col = tc + 16 * q;
-            double v = 0.0;
-            if (row < L && col < nb) {
-                if (WHOLE)
-                    v = (double)static_cast<const TI *>(a.in)[row + (int64_t)col * a.ldi];
-                else
-                    v = src[row + (int64_t)(k0 + col) * lds];
-            }
-            z[r][q] = v;
+            const int row = tr + TR * r, col = tc + 16 * q;
+            z[r][q] = (row < L && col < L) ? (double)static_cast<const TI *>(a.in)[row + (int64_t)col * a.ldi]
+                                           : 0.0;
         }
-    }
+    bool viol = false;
     double *const fbt = &fbs[0][tr];
     double *const rwt = &rws[0][tc];
 
     // One step c = 16 cb + cc, LDS buffer B = c & 1: publication (its column
     // and pivot row are final once step c - 1 is applied), one barrier, the
-    // update.  cb and B are constants after unrolling.
+    // check and the update.  cb and B are constants after unrolling.
     auto step = [&](const int cb, const int cc, const int B) {
-        const int c = 16 * cb + cc, p = k0 + c;
-        const int PR = (16 * cb) / TR;          // register slot of the pivot row
-        const int pt = (16 * cb) % TR + cc;     // its owners' tr
-        if (WHOLE) {
-            // the 16 owners of row p are lanes 16 pt .. 16 pt + 15 of one wave
-            if (wave == (16 * pt) >> 6) {
-                const double piv = readlane_f64(z[PR][cb], (16 * pt + cc) & 63);
-                if (tr == pt) {
-                    const double pinv = 1.0 / piv;
-#pragma unroll
-                    for (int q = 0; q < RC; ++q) {
-                        rwt[B * NBMAX + 16 * q] = (q == cb && tc == cc) ? pinv : z[PR][q] * pinv;
-                        z[PR][q] = 0.0;  // the update adds the scaled row (multiplier -1)
-                    }
-                    if (tc == cc) pvs[B][0] = fabs(piv);
-                }
-            }
-            if (tc == cc) {
-#pragma unroll
-                for (int r = 0; r < RR; ++r) {
-                    fbt[B * LMAX + TR * r] = (r == PR && tr == pt) ? -1.0 : z[r][cb];
-                    z[r][cb] = 0.0;
-                }
-            }
-        } else {
+        const int PR = (16 * cb) / TR;       // register slot of the pivot row
+        const int pt = (16 * cb) % TR + cc;  // its owners' tr
+        // the 16 owners of row c are lanes 16 pt .. 16 pt + 15 of one wave
+        if (wave == (16 * pt) >> 6) {
+            const double piv = readlane_f64(z[PR][cb], (16 * pt + cc) & 63);
             if (tr == pt) {
+                const double pinv = 1.0 / piv;
 #pragma unroll
-                for (int q = 0; q < RC; ++q)
-                    rwt[B * NBMAX + 16 * q] = (q == cb && tc == cc) ? 1.0 : z[PR][q];
-                if (tc == cc) pvs[B][1] = 1.0 / z[PR][cb];
-            }
-            // the owners of column c (half of wave cc / 2 when TR = 32) also
-            // check the step: the pivot, read from its lane, against every
-            // unused row they hold
-            if (wave == (TR * cc) >> 6) {
-                const double piv = readlane_f64(z[PR][cb], (TR * cc + pt) & 63);
-                const double apiv = fabs(piv);
-                bool v = !(apiv > 0.0) || !(apiv <= DBL_MAX);
-#pragma unroll
-                for (int r = 0; r < RR; ++r) {
-                    if (r < PR) continue;  // rows before the pivot: used
-                    const bool used = (r == PR) ? (tr <= pt) : (r + rot >= RR);
-                    v = v || (!used && !(fabs(z[r][cb]) <= apiv));
+                for (int q = 0; q < RC; ++q) {
+                    rwt[B * NBMAX + 16 * q] = (q == cb && tc == cc) ? pinv : z[PR][q] * pinv;
+                    z[PR][q] = 0.0;  // the update adds the scaled row (multiplier -1)
                 }
-                if (tc == cc) viol = viol || v;
+                if (tc == cc) pvs[B] = fabs(piv);
             }
-            if (tc == cc) {
+        }
+        if (tc == cc) {
 #pragma unroll
-                for (int r = 0; r < RR; ++r) {
-                    fbt[B * LMAX + TR * r] = (r == PR && tr == pt) ? 0.0 : z[r][cb];
-                    z[r][cb] = 0.0;
-                }
+            for (int r = 0; r < RR; ++r) {
+                fbt[B * LMAX + TR * r] = (r == PR && tr == pt) ? -1.0 : z[r][cb];
+                z[r][cb] = 0.0;
             }
         }
         __syncthreads();
@@ -464,26 +413,16 @@ __device__ __attribute__((always_inline)) inline bool gj2d_spec(const LeafArgs &
         for (int r = 0; r < RR; ++r) f[r] = fbt[B * LMAX + TR * r];
 #pragma unroll
         for (int q = 0; q < RC; ++q) rv[q] = rwt[B * NBMAX + 16 * q];
-        if (WHOLE) {
-            // check of step c: the pivot, then the unused rows of this thread
-            const double apiv = pvs[B][0];
-            bool v = !(apiv > 0.0) || !(apiv <= DBL_MAX);
+        // check of step c: the pivot, then the unused rows of this thread
+        const double apiv = pvs[B];
+        bool v = !(apiv > 0.0) || !(apiv <= DBL_MAX);
 #pragma unroll
-            for (int r = 0; r < RR; ++r) {
-                if (r < PR) continue;  // rows before the pivot: used
-                const bool used = (r == PR) && (tr <= pt);
-                v = v || (!used && !(fabs(f[r]) <= apiv));
-            }
-            viol = viol || v;
-        } else {
-            const double pinv = pvs[B][1];
-#pragma unroll
-            for (int q = 0; q < RC; ++q) rv[q] = rv[q] * pinv;
-            if (tr == pt) {
-#pragma unroll
-                for (int q = 0; q < RC; ++q) z[PR][q] = rv[q];
-            }
+        for (int r = 0; r < RR; ++r) {
+            if (r < PR) continue;  // rows before the pivot: used
+            const bool used = (r == PR) && (tr <= pt);
+            v = v || (!used && !(fabs(f[r]) <= apiv));
         }
+        viol = viol || v;
 #pragma unroll
         for (int r = 0; r < RR; ++r)
 #pragma unroll
@@ -493,49 +432,390 @@ __device__ __attribute__((always_inline)) inline bool gj2d_spec(const LeafArgs &
 #pragma unroll
     for (int cb = 0; cb < RC; ++cb) {
         for (int cc = 0; cc < 16; cc += 2) {
-            if (16 * cb + cc >= nb) break;
+            if (16 * cb + cc >= L) break;
             step(cb, cc, 0);
-            if (16 * cb + cc + 1 >= nb) break;
+            if (16 * cb + cc + 1 >= L) break;
             step(cb, cc + 1, 1);
         }
     }
     if (__syncthreads_or(viol)) return false;
 
-    if (WHOLE) {
-        TO *out = static_cast<TO *>(a.out);
+    TO *out = static_cast<TO *>(a.out);
 #pragma unroll
-        for (int r = 0; r < RR; ++r)
+    for (int r = 0; r < RR; ++r)
 #pragma unroll
-            for (int q = 0; q < RC; ++q) {
-                const int row = rowr[r], col = tc + 16 * q;
-                if (row < L && col < L) out[row + (int64_t)col * a.ldo] = (TO)z[r][q];
-            }
-    } else {
-#pragma unroll
-        for (int r = 0; r < RR; ++r)
-#pragma unroll
-            for (int q = 0; q < RC; ++q) {
-                const int row = rowr[r], col = tc + 16 * q;
-                if (row < L && col < nb) {
-                    a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[r][q];
-                    a.Up[row + (int64_t)col * L] = z[r][q] - ((row == k0 + col) ? 1.0 : 0.0);
-                }
-            }
-        for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = k0 + c;
-        for (int row = t; row < L; row += NT) {
-            const bool piv = row >= k0 && row < k0 + nb;
-            if (k0 == 0)
-                a.used[row] = piv ? 1 : 0;
-            else if (piv)
-                a.used[row] = 1;
+        for (int q = 0; q < RC; ++q) {
+            const int row = tr + TR * r, col = tc + 16 * q;
+            if (row < L && col < L) out[row + (int64_t)col * a.ldo] = (TO)z[r][q];
         }
-        // pivot rows of the columns outside the panel: rows k0 .. k0 + nb - 1
-        const int nout = L - nb;
-        for (int e = t; e < nb * nout; e += NT) {
-            const int c = e % nb, j = e / nb;
-            const int gj = j < k0 ? j : j + nb;
-            a.Q[c + (int64_t)gj * nb] = src[(k0 + c) + (int64_t)gj * lds];
+    return true;
+}
+
+// -------------------------------------- speculative column-block panel ---
+// The speculative elimination of a panel (nb <= 64 columns from k0, a
+// multiple of 64, L <= 64 RR rows) with one barrier per column block instead
+// of one per step.  Each of the NW waves holds CW = 64 / NW panel columns in
+// full: lane l, slot i of wave w holds row l + 64 ((i + rot) mod RR),
+// rot = k0 / 64, of columns CW w .. CW w + CW - 1, so the pivot row k0 + c of
+// step c sits in slot 0 of lane c and the multipliers of step c are one
+// column of a single wave.  Wave s runs the steps of its own columns alone,
+// taking the pivot row from lane c with readlane, and publishes each step's
+// multipliers, pivot and inverse pivot; after one barrier every other wave
+// applies those steps to its own columns, the pivot row again read from its
+// lane c, and wave s + NW/2 checks them against every unused row.  Wave s + 1
+// has then applied every earlier step to its columns and runs its own; it is
+// the critical path and runs at raised issue priority meanwhile.
+// Each element goes through the operations of gj2d_run in the same order
+// (the pivot row scaled by the inverse pivot, the multipliers taken before
+// the step, the pivot column restarting from 0, one fused multiply-add per
+// step), so when every pivot check passes the outputs are gj2d_run's bit for
+// bit.  Returns whether every check passed; on false nothing is written.
+// Used for panels of 257 .. 512 rows; smaller ones take wpanel_pipe below.
+template <int RR, int NW>
+__device__ __attribute__((always_inline)) inline bool wpanel_spec(const LeafArgs &a) {
+    constexpr int NT = 64 * NW, CW = 64 / NW;  // threads, columns per wave
+    static_assert(CW * NW == 64, "the waves cover 64 columns");
+    __shared__ double fpub[2][RR][CW][64];  // multipliers of a column block's steps
+    __shared__ double ppub[2][2][CW];       // their inverse pivots and pivots
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int L = a.L, k0 = a.k0, nb = a.nb;
+    const double *src = a.in ? static_cast<const double *>(a.in) : a.Z;
+    const int64_t lds = a.in ? a.ldi : a.ldz;
+    const int rot = k0 >> 6;
+    bool viol = (k0 & 63) != 0 || L > 64 * RR || nb > 64 || nb < 1;
+    if (viol) return false;  // the same in every thread
+    int rowr[RR];
+    int rel[RR];  // row - k0 for rows inside the leaf from k0 on, else -1
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+        rowr[i] = lane + 64 * ((i + rot) % RR);
+        rel[i] = (i + rot < RR && rowr[i] < L) ? lane + 64 * i : -1;
+    }
+    double z[RR][CW];
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int col = CW * w + j;
+            z[i][j] = (rowr[i] < L && col < nb) ? src[rowr[i] + (int64_t)(k0 + col) * lds] : 0.0;
         }
+    // the rows before the panel must be the used ones and no other
+    if (w == 0 && k0 > 0) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+            if (rowr[i] < L && ((a.used[rowr[i]] != 0) != (rowr[i] < k0))) viol = true;
+    }
+
+    // Step c = 8w + j on the wave's own columns (j a constant after
+    // unrolling); no branch, so that consecutive steps overlap.
+    auto own_step = [&](const int j, const int B) {
+        const int c = CW * w + j;
+        const double piv = readlane_f64(z[0][j], c);
+        const double pinv = 1.0 / piv;
+        const bool pl = lane == c;
+        double rv[CW], f[RR];
+#pragma unroll
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = (jj == j) ? pinv : readlane_f64(z[0][jj], c) * pinv;
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            f[i] = (i == 0 && pl) ? 0.0 : z[i][j];
+            fpub[B][i][j][lane] = f[i];
+        }
+        if (lane == 0) {
+            ppub[B][0][j] = pinv;
+            ppub[B][1][j] = piv;
+        }
+        // the pivot row (multiplier 0) restarts from the scaled row, the
+        // pivot column from 0
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) {
+                double base = (jj == j) ? 0.0 : z[i][jj];
+                if (i == 0) base = pl ? rv[jj] : base;
+                z[i][jj] = fma(-f[i], rv[jj], base);
+            }
+    };
+    // Step c = 8s + j of another wave's block, applied to this wave's columns,
+    // with the step's multipliers f and inverse pivot pinv already loaded.
+    auto replay_step = [&](const int s, const int j, const double (&f)[RR], const double pinv) {
+        const int c = CW * s + j;
+        const bool pl = lane == c;
+        double rv[CW];
+#pragma unroll
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = readlane_f64(z[0][jj], c) * pinv;
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[i][jj] = fma(-f[i], rv[jj], z[i][jj]);
+        if (pl) {
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[0][jj] = fma(-0.0, rv[jj], rv[jj]);
+        }
+    };
+    // A block's replay reads each step's multipliers one step ahead, so the
+    // LDS latency overlaps the previous step's update.
+    auto replay_block = [&](const int s, const int B) {
+        double fc[RR], pc = ppub[B][0][0];
+#pragma unroll
+        for (int i = 0; i < RR; ++i) fc[i] = fpub[B][i][0][lane];
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            if (CW * s + j >= nb) break;
+            double fn[RR], pn = 0.0;
+            if (j + 1 < CW) {
+                pn = ppub[B][0][j + 1];
+#pragma unroll
+                for (int i = 0; i < RR; ++i) fn[i] = fpub[B][i][j + 1][lane];
+            }
+            replay_step(s, j, fc, pc);
+            if (j + 1 < CW) {
+                pc = pn;
+#pragma unroll
+                for (int i = 0; i < RR; ++i) fc[i] = fn[i];
+            }
+        }
+    };
+    // The checks of block s: each pivot finite and nonzero, and no unused row
+    // (rel > c; the pivot row's published multiplier is 0) larger in
+    // magnitude or not finite.
+    auto check_block = [&](const int s, const int B) {
+        bool v = false;
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int c = CW * s + j;
+            if (c >= nb) break;
+            const double apiv = fabs(ppub[B][1][j]);
+            v = v || !(apiv > 0.0) || !(apiv <= DBL_MAX);
+#pragma unroll
+            for (int i = 0; i < RR; ++i) v = v || (rel[i] > c && !(fabs(fpub[B][i][j][lane]) <= apiv));
+        }
+        viol = viol || v;
+    };
+
+    const int nblk = (nb + CW - 1) / CW;
+    for (int s = 0; s < nblk; ++s) {
+        const int B = s & 1;
+        if (w == s) {
+#pragma unroll
+            for (int j = 0; j < CW; ++j)
+                if (CW * s + j < nb) own_step(j, B);
+            __builtin_amdgcn_s_setprio(0);
+        }
+        __syncthreads();
+        if (w == s + 1) __builtin_amdgcn_s_setprio(2);
+        if (w != s && CW * w < nb) replay_block(s, B);
+        if (w == (s + NW / 2) % NW) check_block(s, B);
+    }
+    if (__syncthreads_or(viol)) return false;
+
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int row = rowr[i], col = CW * w + j;
+            if (row < L && col < nb) {
+                a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
+                a.Up[row + (int64_t)col * L] = z[i][j] - ((row == k0 + col) ? 1.0 : 0.0);
+            }
+        }
+    for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = k0 + c;
+    for (int row = t; row < L; row += NT) {
+        const bool piv = row >= k0 && row < k0 + nb;
+        if (k0 == 0)
+            a.used[row] = piv ? 1 : 0;
+        else if (piv)
+            a.used[row] = 1;
+    }
+    // pivot rows of the columns outside the panel: rows k0 .. k0 + nb - 1
+    const int nout = L - nb;
+    for (int e = t; e < nb * nout; e += NT) {
+        const int c = e % nb, j = e / nb;
+        const int gj = j < k0 ? j : j + nb;
+        a.Q[c + (int64_t)gj * nb] = src[(k0 + c) + (int64_t)gj * lds];
+    }
+    return true;
+}
+
+// The same elimination for panels of up to 256 rows with a flag per step
+// instead of a barrier per column block.  LDS holds the multipliers of all
+// 64 steps (128 KB), so nothing is overwritten: the owner of step c
+// publishes its multipliers, pivot and inverse pivot and then raises the
+// step's flag, and every other wave applies step c as soon as it sees the
+// flag.  Waves run the steps in order, and a step only waits for steps of
+// lower-numbered waves, so every wait ends.  Issue priority goes by distance
+// to ownership (the owner of the running block, then the next two owners),
+// and the checks of block b are done by a wave that replays it anyway
+// (b + 4, else 0; for b = 0 and a panel of at most eight columns, wave 1,
+// which then only follows the steps).
+template <int RR>
+__device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs &a) {
+    constexpr int NW = 8, NT = 64 * NW, CW = 64 / NW;  // waves, threads, columns per wave
+    static_assert(RR <= 4, "the multipliers of 64 steps fill 128 KB of LDS at 256 rows");
+    __shared__ double fst[64][RR][64];  // multipliers of each step, by slot and lane
+    __shared__ double pst[2][64];       // inverse pivot and pivot of each step
+    __shared__ int rdy[64];             // step published
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int L = a.L, k0 = a.k0, nb = a.nb;
+    const double *src = a.in ? static_cast<const double *>(a.in) : a.Z;
+    const int64_t lds = a.in ? a.ldi : a.ldz;
+    const int rot = k0 >> 6;
+    bool viol = (k0 & 63) != 0 || L > 64 * RR || nb > 64 || nb < 1;
+    if (viol) return false;  // the same in every thread
+    if (t < 64) rdy[t] = 0;
+    int rowr[RR];
+    int rel[RR];  // row - k0 for rows inside the leaf from k0 on, else -1
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+        rowr[i] = lane + 64 * ((i + rot) % RR);
+        rel[i] = (i + rot < RR && rowr[i] < L) ? lane + 64 * i : -1;
+    }
+    double z[RR][CW];
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int col = CW * w + j;
+            z[i][j] = (rowr[i] < L && col < nb) ? src[rowr[i] + (int64_t)(k0 + col) * lds] : 0.0;
+        }
+    const int nout = L - nb;
+    if (w == 0 && k0 > 0) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+            if (rowr[i] < L && ((a.used[rowr[i]] != 0) != (rowr[i] < k0))) viol = true;
+    }
+    __syncthreads();  // the flags are cleared
+
+    // The pivot row of a step first takes the scaled row; its multiplier is
+    // 0, so the step's fused multiply-add turns it into fma(-0, rv, rv), the
+    // value gj2d_run gives it.
+    auto own_step = [&](const int j) {
+        const int c = CW * w + j;
+        const double piv = readlane_f64(z[0][j], c);
+        const double pinv = 1.0 / piv;
+        const bool pl = lane == c;
+        double rv[CW], f[RR];
+#pragma unroll
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = (jj == j) ? pinv : readlane_f64(z[0][jj], c) * pinv;
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            f[i] = (i == 0 && pl) ? 0.0 : z[i][j];
+            fst[c][i][lane] = f[i];
+        }
+        if (lane == 0) {
+            pst[0][c] = pinv;
+            pst[1][c] = piv;
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i) z[i][j] = 0.0;  // the pivot column restarts from 0
+        if (pl) {
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[0][jj] = rv[jj];
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[i][jj] = fma(-f[i], rv[jj], z[i][jj]);
+        // the flag last: its release orders it after the stores above
+        if (lane == 0) __hip_atomic_store(&rdy[c], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    auto wait_step = [&](const int c) {
+        while (__hip_atomic_load(&rdy[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+            __builtin_amdgcn_s_sleep(1);
+    };
+    // The checks of step c: the pivot finite and nonzero, and no unused row
+    // (rel > c; the pivot row's published multiplier is 0) larger in
+    // magnitude or not finite.
+    auto check = [&](const int c, const double (&f)[RR]) {
+        const double apiv = fabs(pst[1][c]);
+        bool v = !(apiv > 0.0) | !(apiv <= DBL_MAX);
+#pragma unroll
+        for (int i = 0; i < RR; ++i) v |= (rel[i] > c) & !(fabs(f[i]) <= apiv);
+        viol |= v;
+    };
+    auto replay_step = [&](const int c, const bool chk) {
+        const double pinv = pst[0][c];
+        const bool pl = lane == c;
+        double rv[CW], f[RR];
+#pragma unroll
+        for (int i = 0; i < RR; ++i) f[i] = fst[c][i][lane];
+#pragma unroll
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = readlane_f64(z[0][jj], c) * pinv;
+        if (pl) {
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[0][jj] = rv[jj];
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[i][jj] = fma(-f[i], rv[jj], z[i][jj]);
+        if (chk) check(c, f);
+    };
+    auto check_step = [&](const int c) {
+        double f[RR];
+#pragma unroll
+        for (int i = 0; i < RR; ++i) f[i] = fst[c][i][lane];
+        check(c, f);
+    };
+
+    const bool cols = CW * w < nb;
+    const int nblk = (nb + CW - 1) / CW;
+    for (int b = 0; b < nblk; ++b) {
+        // issue priority by distance to ownership: the owner first, then the
+        // waves whose blocks come next
+        if (w == b)
+            __builtin_amdgcn_s_setprio(3);
+        else if (w == b + 1)
+            __builtin_amdgcn_s_setprio(2);
+        else if (w == b + 2)
+            __builtin_amdgcn_s_setprio(1);
+        // the checking wave of block b (see above)
+        int cw = (b + NW / 2) % NW;
+        if (CW * cw >= nb) cw = b == 0 ? 1 : 0;
+        const bool chk = w == cw;
+        if (w == b) {
+#pragma unroll
+            for (int j = 0; j < CW; ++j)
+                if (CW * b + j < nb) own_step(j);
+            __builtin_amdgcn_s_setprio(0);
+        } else if (cols) {
+            for (int c = CW * b; c < CW * b + CW && c < nb; ++c) {
+                wait_step(c);
+                replay_step(c, chk);
+            }
+        } else if (chk) {
+            for (int c = CW * b; c < CW * b + CW && c < nb; ++c) {
+                wait_step(c);
+                check_step(c);
+            }
+        }
+    }
+    if (__syncthreads_or(viol)) return false;
+
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int row = rowr[i], col = CW * w + j;
+            if (row < L && col < nb) {
+                a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
+                a.Up[row + (int64_t)col * L] = z[i][j] - ((row == k0 + col) ? 1.0 : 0.0);
+            }
+        }
+    for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = k0 + c;
+    for (int row = t; row < L; row += NT) {
+        const bool piv = row >= k0 && row < k0 + nb;
+        if (k0 == 0)
+            a.used[row] = piv ? 1 : 0;
+        else if (piv)
+            a.used[row] = 1;
+    }
+    for (int e = t; e < nb * nout; e += NT) {
+        const int c = e % nb, j = e / nb;
+        const int gj = j < k0 ? j : j + nb;
+        a.Q[c + (int64_t)gj * nb] = src[(k0 + c) + (int64_t)gj * lds];
     }
     return true;
 }
@@ -543,7 +823,17 @@ __device__ __attribute__((always_inline)) inline bool gj2d_spec(const LeafArgs &
 template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
 __device__ __attribute__((always_inline)) inline void gj2d_any(const LeafArgs &a) {
     if (a.spec && *a.spec != 0) {
-        if (gj2d_spec<TR, RR, RC, WHOLE, TI, TO>(a)) return;
+        bool ok;
+        if constexpr (WHOLE) {
+            ok = gj2d_spec<TR, RR, RC, TI, TO>(a);
+        } else {
+            static_assert(TR * RR % 64 == 0, "whole waves hold the panel's rows");
+            if constexpr (TR == 32 && TR * RR <= 256)
+                ok = wpanel_pipe<TR * RR / 64>(a);
+            else
+                ok = wpanel_spec<TR * RR / 64, TR / 4>(a);
+        }
+        if (ok) return;
         if (threadIdx.x == 0) *a.spec = 0;
     }
     gj2d_run<TR, RR, RC, WHOLE, TI, TO>(a);
