@@ -792,18 +792,31 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
             }
         }
     }
-    if (__syncthreads_or(viol)) return false;
-
+    // Outputs the search rewrites in full if a check failed, and that it does
+    // not read, are stored before the vote: U' always, the panel's columns of
+    // Z when the panel is read from the leaf's input.
+    const bool zout = a.in != nullptr;
 #pragma unroll
     for (int i = 0; i < RR; ++i)
 #pragma unroll
         for (int j = 0; j < CW; ++j) {
             const int row = rowr[i], col = CW * w + j;
             if (row < L && col < nb) {
-                a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
                 a.Up[row + (int64_t)col * L] = z[i][j] - ((row == k0 + col) ? 1.0 : 0.0);
+                if (zout) a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
             }
         }
+    if (__syncthreads_or(viol)) return false;
+
+    if (!zout) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                const int row = rowr[i], col = CW * w + j;
+                if (row < L && col < nb) a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
+            }
+    }
     for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = k0 + c;
     for (int row = t; row < L; row += NT) {
         const bool piv = row >= k0 && row < k0 + nb;
