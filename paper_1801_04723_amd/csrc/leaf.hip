@@ -639,7 +639,8 @@ __device__ __attribute__((always_inline)) inline bool wpanel_spec(const LeafArgs
 }
 
 // The same elimination for panels of up to 256 rows with a flag per step
-// instead of a barrier per column block.  LDS holds the multipliers of all
+// instead of a barrier per column block (k0 a multiple of 32 here, and the
+// pivot row k0 + c in slot 0 of lane k0 mod 64 + c).  LDS holds the multipliers of all
 // 64 steps (128 KB), so nothing is overwritten: the owner of step c
 // publishes its multipliers, pivot and inverse pivot and then raises the
 // step's flag, and every other wave applies step c as soon as it sees the
@@ -661,16 +662,18 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
     const int L = a.L, k0 = a.k0, nb = a.nb;
     const double *src = a.in ? static_cast<const double *>(a.in) : a.Z;
     const int64_t lds = a.in ? a.ldi : a.ldz;
-    const int rot = k0 >> 6;
-    bool viol = (k0 & 63) != 0 || L > 64 * RR || nb > 64 || nb < 1;
+    // slot 0 of lane o + c holds row k0 + c, o = k0 mod 64 (0, or 32 for
+    // 32-column panels)
+    const int rot = k0 >> 6, o = k0 & 63;
+    bool viol = o + nb > 64 || L > 64 * RR || nb < 1;
     if (viol) return false;  // the same in every thread
     if (t < 64) rdy[t] = 0;
     int rowr[RR];
-    int rel[RR];  // row - k0 for rows inside the leaf from k0 on, else -1
+    int rel[RR];  // row - k0 for rows inside the leaf (negative before k0), else -1
 #pragma unroll
     for (int i = 0; i < RR; ++i) {
         rowr[i] = lane + 64 * ((i + rot) % RR);
-        rel[i] = (i + rot < RR && rowr[i] < L) ? lane + 64 * i : -1;
+        rel[i] = (i + rot < RR && rowr[i] < L) ? lane + 64 * i - o : -1;
     }
     double z[RR][CW];
 #pragma unroll
@@ -692,13 +695,13 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
     // 0, so the step's fused multiply-add turns it into fma(-0, rv, rv), the
     // value gj2d_run gives it.
     auto own_step = [&](const int j) {
-        const int c = CW * w + j;
-        const double piv = readlane_f64(z[0][j], c);
+        const int c = CW * w + j, pc = o + c;  // step, pivot lane
+        const double piv = readlane_f64(z[0][j], pc);
         const double pinv = 1.0 / piv;
-        const bool pl = lane == c;
+        const bool pl = lane == pc;
         double rv[CW], f[RR];
 #pragma unroll
-        for (int jj = 0; jj < CW; ++jj) rv[jj] = (jj == j) ? pinv : readlane_f64(z[0][jj], c) * pinv;
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = (jj == j) ? pinv : readlane_f64(z[0][jj], pc) * pinv;
 #pragma unroll
         for (int i = 0; i < RR; ++i) {
             f[i] = (i == 0 && pl) ? 0.0 : z[i][j];
@@ -737,12 +740,12 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
     };
     auto replay_step = [&](const int c, const bool chk) {
         const double pinv = pst[0][c];
-        const bool pl = lane == c;
+        const bool pl = lane == o + c;
         double rv[CW], f[RR];
 #pragma unroll
         for (int i = 0; i < RR; ++i) f[i] = fst[c][i][lane];
 #pragma unroll
-        for (int jj = 0; jj < CW; ++jj) rv[jj] = readlane_f64(z[0][jj], c) * pinv;
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = readlane_f64(z[0][jj], o + c) * pinv;
         if (pl) {
 #pragma unroll
             for (int jj = 0; jj < CW; ++jj) z[0][jj] = rv[jj];
