@@ -9,7 +9,7 @@
  * every a - b*c is a rounded product followed by a rounded difference.
  *
  * Storage: every matrix is column-major with a leading dimension, the layout
- * of the paper's matrix blocks (Sec. 3.2, "Block Matrix Data Structure").
+ * of the paper's matrix blocks (the block data structure of Sec. 3.2).
  *
  * Functions
  *   oracle_gemm          C = A * B, plain triple loop, k summed in ascending
