@@ -684,6 +684,17 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
             z[i][j] = (rowr[i] < L && col < nb) ? src[rowr[i] + (int64_t)(k0 + col) * lds] : 0.0;
         }
     const int nout = L - nb;
+    // pivot rows of the columns outside the panel (rows k0 .. k0 + nb - 1,
+    // gathered into Q once every check has passed), loaded now so that the
+    // loads complete during the elimination
+    constexpr int QPT = 4096 * (RR - 1) / NT;  // nb (L - nb) <= 64 (64 RR - 64)
+    double qv[QPT > 0 ? QPT : 1];
+#pragma unroll
+    for (int r = 0; r < QPT; ++r) {
+        const int e = t + NT * r, c = e % nb, j = e / nb;
+        const int gj = j < k0 ? j : j + nb;
+        qv[r] = e < nb * nout ? src[(k0 + c) + (int64_t)gj * lds] : 0.0;
+    }
     if (w == 0 && k0 > 0) {
 #pragma unroll
         for (int i = 0; i < RR; ++i)
@@ -828,10 +839,11 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
         else if (piv)
             a.used[row] = 1;
     }
-    for (int e = t; e < nb * nout; e += NT) {
-        const int c = e % nb, j = e / nb;
+#pragma unroll
+    for (int r = 0; r < QPT; ++r) {
+        const int e = t + NT * r, c = e % nb, j = e / nb;
         const int gj = j < k0 ? j : j + nb;
-        a.Q[c + (int64_t)gj * nb] = src[(k0 + c) + (int64_t)gj * lds];
+        if (e < nb * nout) a.Q[c + (int64_t)gj * nb] = qv[r];
     }
     return true;
 }
