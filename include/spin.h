@@ -102,7 +102,8 @@ typedef struct ihipStream_t *spin_stream_t; /* same object as hipStream_t */
  * Newton residual R = I - A X, the update X + X R and the acceptance
  * residual are formed by spin_gemm_int8's emulation (14 moduli, operands
  * rounded to 47 bits per row / column at order 16384, more below) instead of
- * FP64 matrix cores.  The batched and serving entry points reject it. */
+ * FP64 matrix cores; n <= 131071 (spin_gemm_int8's limit on k), else
+ * SPIN_E_N.  The batched and serving entry points reject it. */
 #define SPIN_REFINE_INT8 32
 
 /* ---- FP64 inversion ------------------------------------------------------- */
@@ -231,6 +232,8 @@ int spin_gemm(int dtype, int64_t m, int64_t n, int64_t k, double alpha,
  *   beta_a, beta_b <= 0: the largest equal pair the moduli allow at this k
  *   (at most 53).  Otherwise 1 + log2(k) + beta_a + beta_b must stay below
  *   log2 of the product of the moduli (SPIN_E_MODE).
+ *   k <= 131071: the matrix cores sum k residue products (|r| <= 128) in
+ *   int32, exact while k 128^2 < 2^31 (SPIN_E_N above).
  * Error against the exact product: |D - A B| <= 2^-beta (m_i sum_k |b_kj| +
  * n_j sum_k |a_ik|) + k 2^-2beta m_i n_j + 2^-53 |D| before the epilogue
  * (m_i, n_j: the largest magnitudes of row i of A and column j of B).  A row

@@ -488,7 +488,7 @@ size_t ozaki_workspace_bytes(int64_t m, int64_t n, int64_t k, int count) {
 }
 
 hipError_t ozaki_product(const OzakiProb &p, void *ws, hipStream_t s) {
-    if (p.moduli < 2 || p.moduli > kOzakiMaxModuli) return hipErrorInvalidValue;
+    if (p.moduli < 2 || p.moduli > kOzakiMaxModuli || p.k > kOzakiMaxK) return hipErrorInvalidValue;
     if (p.m <= 0 || p.n <= 0) return hipSuccess;
     const int64_t m = p.m, n = p.n, k = p.k;
     const int64_t tile = tile_for(m, n);

@@ -765,6 +765,7 @@ int spin_invert_mixed(const double *A, int64_t n, int64_t lda, double *Ainv, int
     const bool emu = (mode & SPIN_REFINE_INT8) != 0;
     const int pmode = mode & ~(SPIN_SYMMETRIC | SPIN_REFINE_INT8);
     if (!is_mixed_mode(pmode) || ns_steps < 0 || ns_steps > kNormSlots) return SPIN_E_MODE;
+    if (emu && n > kOzakiMaxK) return SPIN_E_N;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(g_mu);
     Plan P = sym ? make_plan_spd(n, n, n, leaf) : make_plan(n, n, n, leaf);
@@ -930,7 +931,7 @@ int spin_gemm_int8(int64_t m, int64_t n, int64_t k, const double *A, int64_t lda
                    int64_t ldb, int epilogue, const double *C0, int64_t ldc, double *D, int64_t ldd,
                    int moduli, int beta_a, int beta_b, spin_stream_t stream) {
     if (epilogue < 0 || epilogue > 2 || moduli < 2 || moduli > kOzakiMaxModuli) return SPIN_E_MODE;
-    if (m < 0 || n < 0 || k < 0 || m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > INT32_MAX / 2)
+    if (m < 0 || n < 0 || k < 0 || m > INT32_MAX / 2 || n > INT32_MAX / 2 || k > kOzakiMaxK)
         return SPIN_E_N;
     if (epilogue == 1 && m != n) return SPIN_E_N;
     if (!D || (k > 0 && (!A || !B)) || (epilogue == 2 && !C0)) return SPIN_E_NULL;

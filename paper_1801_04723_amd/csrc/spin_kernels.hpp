@@ -117,6 +117,10 @@ constexpr double kNsTol = 1e-12;
 // Moduli of the refinement's INT8-emulated products (SPIN_REFINE_INT8): 14
 // give about 110 bits of modulus, operands of 47 bits at order 16384.
 constexpr int kRefineModuli = 14;
+// Longest inner dimension of an INT8-emulated product: the matrix cores sum
+// k products of symmetric residues (|r| <= 128) in int32, exact while
+// k 128^2 < 2^31.
+constexpr int64_t kOzakiMaxK = 131071;
 hipError_t ns_final(const double *r2, const double *a2, const double *x2, double tol, int *status,
                     hipStream_t s);
 hipError_t cast_f64_to_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t m,

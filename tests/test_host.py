@@ -446,6 +446,24 @@ def test_server_symmetric_mode_validation():
     assert rc == -6
 
 
+def test_int8_emulation_inner_dimension_limit():
+    """The INT8 residue products accumulate k terms of at most 128^2 in int32:
+    k above 131071 could wrap, so it is rejected before any GPU work, for the
+    product and for the INT8-refined inversion."""
+    L = S.lib()
+    p = ctypes.c_void_p
+    A, B, D = p(0x10000000), p(0x20000000), p(0x30000000)
+    big = 131072
+    assert L.spin_gemm_int8(4, 4, big, A, 4, B, big, 0, None, 1, D, 4, 14, 0, 0, p(0)) == -2
+    assert L.spin_gemm_int8(4, 4, 4, A, 4, B, 4, 3, None, 1, D, 4, 14, 0, 0, p(0)) == -6
+    # far-apart fake buffers, so that the order-131072 ranges do not overlap
+    assert L.spin_invert_mixed(p(1 << 44), big, big, p(1 << 46), big, 256,
+                               S.MIXED_FP32 | S.REFINE_INT8, 2, None, p(0)) == -2
+    assert L.spin_invert_mixed(p(1 << 44), big, big, p(1 << 46), big, 256, S.MIXED_FP32, 9, None,
+                               p(0)) == -6
+    assert 128 * 128 * 131071 < 2 ** 31 <= 128 * 128 * big
+
+
 def test_symmetric_mixed_modes_validation():
     """Mixed modes with SYMMETRIC: the symmetric schedule's footprint (no more
     than the plain one's) in the server, accepted by spin_invert_mixed's
