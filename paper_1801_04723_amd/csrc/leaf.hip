@@ -119,6 +119,10 @@ struct LeafArgs {
     // try the speculative elimination first; a failed attempt sets it to 0 so
     // that the later leaves of the same inversion go straight to the search.
     int *spec;
+    // Two-workgroup panels: this panel's exchange area (multipliers and
+    // pivots of its 64 steps) and its verdict and decision words.
+    double *xg;
+    int *xc;
 };
 
 template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
@@ -848,6 +852,335 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
     return true;
 }
 
+// ------------------------------------------------- two-workgroup panel ---
+// The pipelined elimination of a full 64-column panel of at most 256 rows on
+// two workgroups (two CUs), each holding 32 of its columns (eight waves of
+// four), so that each CU replays half of the steps' updates.  Workgroup h
+// owns steps 32h .. 32h + 31 and runs them as wpanel_pipe does (LDS flags);
+// the wave that checks a local step also stores its multipliers, pivot and
+// inverse pivot to the panel's exchange area in device memory, and the other
+// workgroup replays the step from there.
+//
+// The exchange area is filled with a signalling-NaN pattern before the
+// leaf's panels (leaf_duo_reset), so a value read back is either that
+// pattern (not yet stored: read again) or the stored value: every 8-byte
+// access is single-copy atomic, and no flag or ordering between stores is
+// needed.  The loads and stores are device-coherent (agent scope), and the
+// next step's values are loaded before the current step's update.
+//
+// Every wait is bounded.  Workgroup 1 posts its verdict (all its checks
+// passed, or not) and waits for workgroup 0's decision; workgroup 0 waits
+// for that verdict, decides (commit only if both workgroups' checks passed
+// and nothing timed out), and posts the decision.  Workgroup 0 is dispatched
+// before workgroup 1, so a running workgroup 1 always gets a decision.  On
+// commit both write their halves of the outputs; on abort neither writes and
+// workgroup 0 runs the search (leaf_duo).  A value equal to the pattern in
+// the input only makes a wait run out, which aborts to the search.
+constexpr unsigned long long kDuoPoison = 0x7FF4DEADBEEF0001ull;  // a signalling NaN
+constexpr int kDuoSpin = 1 << 15;        // polls of a data wait (about 64 clocks each and more)
+constexpr int kDuoDecideSpin = 1 << 24;  // polls of workgroup 1's wait for the decision
+
+__device__ inline double ld_agent(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int ld_agent_i(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_agent_i(int *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool is_poison(double v) {
+    return (unsigned long long)__double_as_longlong(v) == kDuoPoison;
+}
+
+// Doubles of one panel's exchange area at RR slots per lane: the 64 steps'
+// multipliers [step][slot][lane], then the inverse pivots and the pivots.
+template <int RR>
+constexpr int duo_panel_doubles() { return 64 * RR * 64 + 2 * 64; }
+// Ints of one panel's decision area: verdict of workgroup 1, decision.
+constexpr int kDuoPanelInts = 2;
+
+template <int RR>
+__device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs &a) {
+    constexpr int NW = 8, NT = 512, CW = 4, HALF = 32;  // waves, threads, columns per wave, per workgroup
+    static_assert(RR <= 4 && CW * NW == HALF, "two workgroups of 32 columns, at most 256 rows");
+    __shared__ double fst[HALF][RR][64];  // this workgroup's steps' multipliers
+    __shared__ double pst[2][HALF];       // their inverse pivots and pivots
+    __shared__ int rdy[HALF];
+    const int h = blockIdx.x;  // 0 or 1: columns and steps 32h .. 32h + 31
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int L = a.L, k0 = a.k0, nb = a.nb;
+    const double *src = a.in ? static_cast<const double *>(a.in) : a.Z;
+    const int64_t lds = a.in ? a.ldi : a.ldz;
+    const int rot = k0 >> 6;
+    if ((k0 & 63) != 0 || nb != 64 || L > 64 * RR || L <= 64 || !a.xg || !a.xc)
+        return false;  // the same in both workgroups
+    double *gf = a.xg;                // [64][RR][64]
+    double *gp = a.xg + 64 * RR * 64;  // [2][64]
+    int *verdict1 = a.xc, *decision = a.xc + 1;
+    if (t < HALF) rdy[t] = 0;
+    int rowr[RR];
+    int rel[RR];  // row - k0 for rows inside the leaf from k0 on, else -1
+#pragma unroll
+    for (int i = 0; i < RR; ++i) {
+        rowr[i] = lane + 64 * ((i + rot) % RR);
+        rel[i] = (i + rot < RR && rowr[i] < L) ? lane + 64 * i : -1;
+    }
+    double z[RR][CW];
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int col = HALF * h + CW * w + j;
+            z[i][j] = rowr[i] < L ? src[rowr[i] + (int64_t)(k0 + col) * lds] : 0.0;
+        }
+    // this workgroup's half of the pivot rows of the outside columns (Q)
+    const int nout = L - nb, qtot = nb * nout, qhalf = (qtot + 1) / 2;
+    constexpr int QPT = (4096 * (RR - 1) / 2 + NT - 1) / NT;
+    double qv[QPT];
+#pragma unroll
+    for (int r = 0; r < QPT; ++r) {
+        const int e = h * qhalf + t + NT * r, c = e % nb, j = e / nb;
+        const int gj = j < k0 ? j : j + nb;
+        qv[r] = (t + NT * r < qhalf && e < qtot) ? src[(k0 + c) + (int64_t)gj * lds] : 0.0;
+    }
+    bool viol = false;
+    if (h == 0 && w == 0 && k0 > 0) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+            if (rowr[i] < L && ((a.used[rowr[i]] != 0) != (rowr[i] < k0))) viol = true;
+    }
+    __syncthreads();  // the flags are cleared
+
+    auto own_step = [&](const int j) {
+        const int c = HALF * h + CW * w + j, lc = c - HALF * h;
+        const double piv = readlane_f64(z[0][j], c);
+        const double pinv = 1.0 / piv;
+        const bool pl = lane == c;
+        double rv[CW], f[RR];
+#pragma unroll
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = (jj == j) ? pinv : readlane_f64(z[0][jj], c) * pinv;
+#pragma unroll
+        for (int i = 0; i < RR; ++i) {
+            f[i] = (i == 0 && pl) ? 0.0 : z[i][j];
+            fst[lc][i][lane] = f[i];
+        }
+        if (lane == 0) {
+            pst[0][lc] = pinv;
+            pst[1][lc] = piv;
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i) z[i][j] = 0.0;  // the pivot column restarts from 0
+        if (pl) {
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[0][jj] = rv[jj];
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[i][jj] = fma(-f[i], rv[jj], z[i][jj]);
+        if (lane == 0) __hip_atomic_store(&rdy[lc], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    // the update of step c with its multipliers and inverse pivot
+    auto apply = [&](const int c, const double (&f)[RR], const double pinv) {
+        const bool pl = lane == c;
+        double rv[CW];
+#pragma unroll
+        for (int jj = 0; jj < CW; ++jj) rv[jj] = readlane_f64(z[0][jj], c) * pinv;
+        if (pl) {
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[0][jj] = rv[jj];
+        }
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int jj = 0; jj < CW; ++jj) z[i][jj] = fma(-f[i], rv[jj], z[i][jj]);
+    };
+    // a local step of another wave; the checking wave also checks it and
+    // stores it to the exchange area
+    auto local_step = [&](const int c, const bool chk) {
+        const int lc = c - HALF * h;
+        while (__hip_atomic_load(&rdy[lc], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
+            __builtin_amdgcn_s_sleep(1);
+        const double pinv = pst[0][lc];
+        double f[RR];
+#pragma unroll
+        for (int i = 0; i < RR; ++i) f[i] = fst[lc][i][lane];
+        apply(c, f, pinv);
+        if (chk) {
+            const double piv = pst[1][lc];
+            const double apiv = fabs(piv);
+            bool v = !(apiv > 0.0) | !(apiv <= DBL_MAX);
+#pragma unroll
+            for (int i = 0; i < RR; ++i) {
+                v |= (rel[i] > c) & !(fabs(f[i]) <= apiv);
+                st_agent(&gf[((int64_t)c * RR + i) * 64 + lane], f[i]);
+            }
+            viol |= v;
+            if (lane == 0) {
+                st_agent(&gp[c], pinv);
+                st_agent(&gp[64 + c], piv);
+            }
+        }
+    };
+    // The other workgroup's 32 steps c0 .. c0 + 31, each read back from the
+    // exchange area once every lane sees stored values.  The values of the
+    // next DEPTH steps are in flight while a step is applied (a device-
+    // coherent load takes about a microsecond, several steps' work); false if
+    // a wait ran out.
+    constexpr int DEPTH = 6;
+    auto remote_steps = [&](const int c0) -> bool {
+        double rf[DEPTH][RR], rp[DEPTH];
+        auto load = [&](const int c, double (&ff)[RR], double &pp) {
+#pragma unroll
+            for (int i = 0; i < RR; ++i) ff[i] = ld_agent(&gf[((int64_t)c * RR + i) * 64 + lane]);
+            pp = ld_agent(&gp[c]);
+        };
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) load(c0 + d, rf[d], rp[d]);
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) {
+            const int c = c0 + k, d = k % DEPTH;
+            auto missing = [&](const double (&ff)[RR], const double pp) {
+                bool bad = is_poison(pp);
+#pragma unroll
+                for (int i = 0; i < RR; ++i) bad |= is_poison(ff[i]);
+                return __any(bad) != 0;
+            };
+            // The first look is outside any loop, so the loads of the later
+            // steps stay in flight; a step not yet stored is read again into
+            // other registers until it is.
+            if (missing(rf[d], rp[d])) {
+                double tf[RR], tp;
+                int spins = 0;
+                do {
+                    if (++spins > kDuoSpin) return false;
+                    __builtin_amdgcn_s_sleep(2);
+                    load(c, tf, tp);
+                } while (missing(tf, tp));
+#pragma unroll
+                for (int i = 0; i < RR; ++i) rf[d][i] = tf[i];
+                rp[d] = tp;
+            }
+            double f[RR];
+#pragma unroll
+            for (int i = 0; i < RR; ++i) f[i] = rf[d][i];
+            const double pinv = rp[d];
+            if (k + DEPTH < HALF) load(c + DEPTH, rf[d], rp[d]);
+            apply(c, f, pinv);
+        }
+        return true;
+    };
+
+    bool ok = true;
+    // steps 0 .. 31 (workgroup 0's), then 32 .. 63 (workgroup 1's)
+    for (int half = 0; half < 2; ++half) {
+        if (half != h) {
+            if (ok) ok = remote_steps(HALF * half);
+            continue;
+        }
+        for (int b = 0; b < NW; ++b) {
+            // issue priority by distance to ownership
+            if (w == b)
+                __builtin_amdgcn_s_setprio(3);
+            else if (w == b + 1)
+                __builtin_amdgcn_s_setprio(2);
+            else if (w == b + 2)
+                __builtin_amdgcn_s_setprio(1);
+            const bool chk = w == (b + NW / 2) % NW;
+            if (w == b) {
+#pragma unroll
+                for (int j = 0; j < CW; ++j) own_step(j);
+                __builtin_amdgcn_s_setprio(0);
+            } else {
+                for (int c = HALF * h + CW * b; c < HALF * h + CW * b + CW; ++c) local_step(c, chk);
+            }
+        }
+    }
+    __builtin_amdgcn_s_setprio(0);
+    const bool bad = __syncthreads_or(viol || !ok);
+
+    // verdict and decision
+    __shared__ int commit_s;
+    if (t == 0) {
+        if (h == 1) {
+            st_agent_i(verdict1, bad ? 1 : 0);
+            int d = -1;
+            for (int spins = 0; spins < kDuoDecideSpin; ++spins) {
+                d = ld_agent_i(decision);
+                if (d >= 0) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+            commit_s = d == 1;
+        } else {
+            int v = -1;
+            for (int spins = 0; !bad && spins < kDuoSpin; ++spins) {
+                v = ld_agent_i(verdict1);
+                if (v >= 0) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+            const bool c = !bad && v == 0;
+            st_agent_i(decision, c ? 1 : 0);
+            commit_s = c;
+        }
+    }
+    __syncthreads();
+    if (!commit_s) return false;
+
+#pragma unroll
+    for (int r = 0; r < QPT; ++r) {
+        const int e = h * qhalf + t + NT * r, c = e % nb, j = e / nb;
+        const int gj = j < k0 ? j : j + nb;
+        if (t + NT * r < qhalf && e < qtot) a.Q[c + (int64_t)gj * nb] = qv[r];
+    }
+#pragma unroll
+    for (int i = 0; i < RR; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const int row = rowr[i], col = HALF * h + CW * w + j;
+            if (row < L) {
+                a.Up[row + (int64_t)col * L] = z[i][j] - ((row == k0 + col) ? 1.0 : 0.0);
+                a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
+            }
+        }
+    if (h == 0) {
+        for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = k0 + c;
+        for (int row = t; row < L; row += NT) {
+            const bool piv = row >= k0 && row < k0 + nb;
+            if (k0 == 0)
+                a.used[row] = piv ? 1 : 0;
+            else if (piv)
+                a.used[row] = 1;
+        }
+    }
+    return true;
+}
+
+// A full panel of a leaf of order 129 .. 256 on two workgroups; on abort
+// (or with speculation off) workgroup 0 runs the search kernel.
+__global__ void __launch_bounds__(512) leaf_duo(LeafArgs a) {
+    if (a.spec && *a.spec != 0) {
+        if (wpanel_duo<4>(a)) return;
+        if (blockIdx.x != 0) return;
+        if (threadIdx.x == 0) *a.spec = 0;
+    } else if (blockIdx.x != 0) {
+        return;
+    }
+    gj2d_run<32, 8, 4, false, double, double>(a);
+}
+
+// Fills the exchange areas of a leaf's two-workgroup panels: every value
+// with the pattern, every verdict and decision word with -1.
+__global__ void __launch_bounds__(256) leaf_duo_reset(double *xg, int64_t nd, int *xc, int ni) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < nd) xg[e] = __longlong_as_double((long long)kDuoPoison);
+    if (e < ni) xc[e] = -1;
+}
+
 template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
 __device__ __attribute__((always_inline)) inline void gj2d_any(const LeafArgs &a) {
     if (a.spec && *a.spec != 0) {
@@ -1121,6 +1454,16 @@ hipError_t panel_launch(const PanelArgs &pa, hipStream_t s) {
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Leaves of order 129 .. 256 run their full panels on two workgroups
+// (leaf_duo), with an exchange area per panel.
+constexpr int kDuoPanels = 4;
+bool duo_leaf(int64_t L) { return L > 128 && L <= 256; }
+size_t duo_bytes(int64_t L) {
+    return duo_leaf(L) ? align256(sizeof(double) * kDuoPanels * duo_panel_doubles<4>()) +
+                             align256(sizeof(int) * kDuoPanels * kDuoPanelInts)
+                       : 0;
+}
+
 }  // namespace
 
 size_t leaf_scratch_bytes(int64_t L) {
@@ -1128,7 +1471,7 @@ size_t leaf_scratch_bytes(int64_t L) {
     const int64_t nb = panel_width(L);
     return align256(sizeof(double) * L * L) + align256(sizeof(double) * L * nb) +
            align256(sizeof(double) * L * nb) + align256(sizeof(int) * L) +
-           align256(sizeof(int) * L);
+           align256(sizeof(int) * L) + duo_bytes(L);
 }
 
 hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DType out_dt,
@@ -1177,6 +1520,22 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
     int *rsel = reinterpret_cast<int *>(p);
     p += align256(sizeof(int) * L);
     int *used = reinterpret_cast<int *>(p);
+    p += align256(sizeof(int) * L);
+    double *xg = nullptr;
+    int *xc = nullptr;
+    if (duo_leaf(L)) {
+        xg = reinterpret_cast<double *>(p);
+        p += align256(sizeof(double) * kDuoPanels * duo_panel_doubles<4>());
+        xc = reinterpret_cast<int *>(p);
+        LaunchInfo li{"leaf_duo_reset", 0.0, 8.0 * kDuoPanels * duo_panel_doubles<4>()};
+        cb(li, 0);
+        const int64_t nd = (int64_t)kDuoPanels * duo_panel_doubles<4>();
+        hipLaunchKernelGGL(leaf_duo_reset, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, s, xg, nd,
+                           xc, kDuoPanels * kDuoPanelInts);
+        hipError_t e = hipGetLastError();
+        cb(li, 1);
+        if (e != hipSuccess) return e;
+    }
 
     const int nblk = (int)(((int64_t)L * L + 255) / 256);
     // Up to order 512 an FP64 input is read in place by the first panel and
@@ -1221,7 +1580,12 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                 la.rsel = rsel;
                 la.Up = Up;
                 la.Q = Q;
-                if (L <= 256)
+                if (duo_leaf(L) && w == 64 && k0 % 64 == 0 && k0 / 64 < kDuoPanels) {
+                    la.xg = xg + (int64_t)(k0 / 64) * duo_panel_doubles<4>();
+                    la.xc = xc + (k0 / 64) * kDuoPanelInts;
+                    hipLaunchKernelGGL(leaf_duo, dim3(2), dim3(512), 0, s, la);
+                    e = hipGetLastError();
+                } else if (L <= 256)
                     e = gj2d_launch<kPanel256TR, 256 / kPanel256TR, 4, false, double, double>(la, s);
                 else
                     e = gj2d_launch<kPanel512TR, 512 / kPanel512TR, 4, false, double, double>(la, s);
