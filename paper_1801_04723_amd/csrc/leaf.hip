@@ -857,16 +857,16 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
 // two workgroups (two CUs), each holding 32 of its columns (eight waves of
 // four), so that each CU replays half of the steps' updates.  Workgroup h
 // owns steps 32h .. 32h + 31 and runs them as wpanel_pipe does (LDS flags);
-// the wave that checks a local step also stores its multipliers, pivot and
-// inverse pivot to the panel's exchange area in device memory, and the other
-// workgroup replays the step from there.
+// the wave that owns a step also stores its multipliers and inverse pivot to
+// the panel's exchange area in device memory, and the other workgroup
+// replays the step from there.
 //
 // The exchange area is filled with a signalling-NaN pattern before the
 // leaf's panels (leaf_duo_reset), so a value read back is either that
 // pattern (not yet stored: read again) or the stored value: every 8-byte
 // access is single-copy atomic, and no flag or ordering between stores is
 // needed.  The loads and stores are device-coherent (agent scope), and the
-// next step's values are loaded before the current step's update.
+// values of the step after next are loaded before the current step's update.
 //
 // Every wait is bounded.  Workgroup 1 posts its verdict (all its checks
 // passed, or not) and waits for workgroup 0's decision; workgroup 0 waits
@@ -897,9 +897,9 @@ __device__ inline bool is_poison(double v) {
 }
 
 // Doubles of one panel's exchange area at RR slots per lane: the 64 steps'
-// multipliers [step][slot][lane], then the inverse pivots and the pivots.
+// multipliers [step][slot][lane], then the inverse pivots.
 template <int RR>
-constexpr int duo_panel_doubles() { return 64 * RR * 64 + 2 * 64; }
+constexpr int duo_panel_doubles() { return 64 * RR * 64 + 64; }
 // Ints of one panel's decision area: verdict of workgroup 1, decision.
 constexpr int kDuoPanelInts = 2;
 
@@ -920,7 +920,7 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
     if ((k0 & 63) != 0 || nb != 64 || L > 64 * RR || L <= 64 || !a.xg || !a.xc)
         return false;  // the same in both workgroups
     double *gf = a.xg;                // [64][RR][64]
-    double *gp = a.xg + 64 * RR * 64;  // [2][64]
+    double *gp = a.xg + 64 * RR * 64;  // [64]
     int *verdict1 = a.xc, *decision = a.xc + 1;
     if (t < HALF) rdy[t] = 0;
     int rowr[RR];
@@ -974,6 +974,9 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
             pst[1][lc] = piv;
         }
 #pragma unroll
+        for (int i = 0; i < RR; ++i) st_agent(&gf[((int64_t)c * RR + i) * 64 + lane], f[i]);
+        if (lane == 0) st_agent(&gp[c], pinv);
+#pragma unroll
         for (int i = 0; i < RR; ++i) z[i][j] = 0.0;  // the pivot column restarts from 0
         if (pl) {
 #pragma unroll
@@ -1000,8 +1003,7 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
 #pragma unroll
             for (int jj = 0; jj < CW; ++jj) z[i][jj] = fma(-f[i], rv[jj], z[i][jj]);
     };
-    // a local step of another wave; the checking wave also checks it and
-    // stores it to the exchange area
+    // a local step of another wave, checked by the checking wave
     auto local_step = [&](const int c, const bool chk) {
         const int lc = c - HALF * h;
         while (__hip_atomic_load(&rdy[lc], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
@@ -1016,23 +1018,17 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
             const double apiv = fabs(piv);
             bool v = !(apiv > 0.0) | !(apiv <= DBL_MAX);
 #pragma unroll
-            for (int i = 0; i < RR; ++i) {
-                v |= (rel[i] > c) & !(fabs(f[i]) <= apiv);
-                st_agent(&gf[((int64_t)c * RR + i) * 64 + lane], f[i]);
-            }
+            for (int i = 0; i < RR; ++i) v |= (rel[i] > c) & !(fabs(f[i]) <= apiv);
             viol |= v;
-            if (lane == 0) {
-                st_agent(&gp[c], pinv);
-                st_agent(&gp[64 + c], piv);
-            }
         }
     };
     // The other workgroup's 32 steps c0 .. c0 + 31, each read back from the
     // exchange area once every lane sees stored values.  The values of the
-    // next DEPTH steps are in flight while a step is applied (a device-
-    // coherent load takes about a microsecond, several steps' work); false if
-    // a wait ran out.
-    constexpr int DEPTH = 6;
+    // next DEPTH steps are in flight while a step is applied: a device-
+    // coherent load takes about as long as two steps' work, and a load issued
+    // further ahead is more often issued before the value is stored and must
+    // be repeated.  False if a wait ran out.
+    constexpr int DEPTH = 2;
     auto remote_steps = [&](const int c0) -> bool {
         double rf[DEPTH][RR], rp[DEPTH];
         auto load = [&](const int c, double (&ff)[RR], double &pp) {
