@@ -857,25 +857,31 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
 // two workgroups (two CUs), each holding 32 of its columns (eight waves of
 // four), so that each CU replays half of the steps' updates.  Workgroup h
 // owns steps 32h .. 32h + 31 and runs them as wpanel_pipe does (LDS flags);
-// the wave that owns a step also stores its multipliers and inverse pivot to
-// the panel's exchange area in device memory, and the other workgroup
+// the wave that owned the previous column block, which is then caught up and
+// far from its next turn, stores each step's multipliers and inverse pivot
+// to the panel's exchange area in device memory, and the other workgroup
 // replays the step from there.
 //
-// The exchange area is filled with a signalling-NaN pattern before the
-// leaf's panels (leaf_duo_reset), so a value read back is either that
-// pattern (not yet stored: read again) or the stored value: every 8-byte
-// access is single-copy atomic, and no flag or ordering between stores is
-// needed.  The loads and stores are device-coherent (agent scope), and the
-// values of the step after next are loaded before the current step's update.
+// The exchange area holds a signalling-NaN pattern before the panel (filled
+// by leaf_duo_reset, or by the previous leaf's leaf_unpermute), so a value
+// read back is either that pattern (not yet stored: read again) or the
+// stored value: every 8-byte access is single-copy atomic, and no flag or
+// ordering between stores is needed.  The loads and stores are device-
+// coherent (agent scope), and the values of the step after next are loaded
+// before the current step's update.
 //
-// Every wait is bounded.  Workgroup 1 posts its verdict (all its checks
-// passed, or not) and waits for workgroup 0's decision; workgroup 0 waits
-// for that verdict, decides (commit only if both workgroups' checks passed
-// and nothing timed out), and posts the decision.  Workgroup 0 is dispatched
-// before workgroup 1, so a running workgroup 1 always gets a decision.  On
-// commit both write their halves of the outputs; on abort neither writes and
-// workgroup 0 runs the search (leaf_duo).  A value equal to the pattern in
-// the input only makes a wait run out, which aborts to the search.
+// Every wait is bounded.  Workgroup 0 posts a verdict on its own steps when
+// they are done.  Workgroup 1 posts its verdict (all its checks passed, or
+// not) and waits for workgroup 0's decision; workgroup 0 waits for that
+// verdict, decides (commit only if both workgroups' checks passed and
+// nothing timed out), and posts the decision.  Workgroup 0 is dispatched
+// before workgroup 1, so a running workgroup 1 always gets a decision.
+// Outputs that are not the search's input are stored before the decision
+// where they cannot differ from the search's (workgroup 0's own, which it
+// orders before the search; workgroup 1's once both verdicts passed); the
+// rest on commit.  On abort workgroup 0 runs the search (leaf_duo).  A value
+// equal to the pattern in the input only makes a wait run out, which aborts
+// to the search.
 constexpr unsigned long long kDuoPoison = 0x7FF4DEADBEEF0001ull;  // a signalling NaN
 constexpr int kDuoSpin = 1 << 15;        // polls of a data wait (about 64 clocks each and more)
 constexpr int kDuoDecideSpin = 1 << 24;  // polls of workgroup 1's wait for the decision
@@ -900,8 +906,9 @@ __device__ inline bool is_poison(double v) {
 // multipliers [step][slot][lane], then the inverse pivots.
 template <int RR>
 constexpr int duo_panel_doubles() { return 64 * RR * 64 + 64; }
-// Ints of one panel's decision area: verdict of workgroup 1, decision.
-constexpr int kDuoPanelInts = 2;
+// Ints of one panel's decision area: verdict of workgroup 1, decision,
+// verdict of workgroup 0 on its own steps.
+constexpr int kDuoPanelInts = 3;
 
 template <int RR>
 __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs &a) {
@@ -921,7 +928,7 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
         return false;  // the same in both workgroups
     double *gf = a.xg;                // [64][RR][64]
     double *gp = a.xg + 64 * RR * 64;  // [64]
-    int *verdict1 = a.xc, *decision = a.xc + 1;
+    int *verdict1 = a.xc, *decision = a.xc + 1, *verdict0 = a.xc + 2;
     if (t < HALF) rdy[t] = 0;
     int rowr[RR];
     int rel[RR];  // row - k0 for rows inside the leaf from k0 on, else -1
@@ -948,6 +955,39 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
         const int gj = j < k0 ? j : j + nb;
         qv[r] = (t + NT * r < qhalf && e < qtot) ? src[(k0 + c) + (int64_t)gj * lds] : 0.0;
     }
+    // output stores: Q (this workgroup's half), U' with or without Z, Z
+    auto store_q = [&]() {
+#pragma unroll
+        for (int r = 0; r < QPT; ++r) {
+            const int e = h * qhalf + t + NT * r, c = e % nb, j = e / nb;
+            const int gj = j < k0 ? j : j + nb;
+            if (t + NT * r < qhalf && e < qtot) a.Q[c + (int64_t)gj * nb] = qv[r];
+        }
+    };
+    auto store_up = [&](const bool with_z) {
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                const int row = rowr[i], col = HALF * h + CW * w + j;
+                if (row < L) {
+                    a.Up[row + (int64_t)col * L] = z[i][j] - ((row == k0 + col) ? 1.0 : 0.0);
+                    if (with_z) a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
+                }
+            }
+    };
+    auto store_z = [&]() {
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                const int row = rowr[i], col = HALF * h + CW * w + j;
+                if (row < L) a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
+            }
+    };
+    // Z may be written before the decision only when the panel is read from
+    // the leaf's input; otherwise Z holds the search's input.
+    const bool z_early = a.in != nullptr;
     bool viol = false;
     if (h == 0 && w == 0 && k0 > 0) {
 #pragma unroll
@@ -973,9 +1013,6 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
             pst[0][lc] = pinv;
             pst[1][lc] = piv;
         }
-#pragma unroll
-        for (int i = 0; i < RR; ++i) st_agent(&gf[((int64_t)c * RR + i) * 64 + lane], f[i]);
-        if (lane == 0) st_agent(&gp[c], pinv);
 #pragma unroll
         for (int i = 0; i < RR; ++i) z[i][j] = 0.0;  // the pivot column restarts from 0
         if (pl) {
@@ -1003,8 +1040,9 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
 #pragma unroll
             for (int jj = 0; jj < CW; ++jj) z[i][jj] = fma(-f[i], rv[jj], z[i][jj]);
     };
-    // a local step of another wave, checked by the checking wave
-    auto local_step = [&](const int c, const bool chk) {
+    // a local step of another wave, checked by the checking wave and passed
+    // to the other workgroup by the forwarding wave
+    auto local_step = [&](const int c, const bool chk, const bool fwd) {
         const int lc = c - HALF * h;
         while (__hip_atomic_load(&rdy[lc], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0)
             __builtin_amdgcn_s_sleep(1);
@@ -1012,6 +1050,11 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
         double f[RR];
 #pragma unroll
         for (int i = 0; i < RR; ++i) f[i] = fst[lc][i][lane];
+        if (fwd) {
+#pragma unroll
+            for (int i = 0; i < RR; ++i) st_agent(&gf[((int64_t)c * RR + i) * 64 + lane], f[i]);
+            if (lane == 0) st_agent(&gp[c], pinv);
+        }
         apply(c, f, pinv);
         if (chk) {
             const double piv = pst[1][lc];
@@ -1087,24 +1130,55 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
                 __builtin_amdgcn_s_setprio(2);
             else if (w == b + 2)
                 __builtin_amdgcn_s_setprio(1);
+            // the previous owner, just caught up, forwards the block's steps
             const bool chk = w == (b + NW / 2) % NW;
+            const bool fwd = w == (b + NW - 1) % NW;
             if (w == b) {
 #pragma unroll
                 for (int j = 0; j < CW; ++j) own_step(j);
                 __builtin_amdgcn_s_setprio(0);
             } else {
-                for (int c = HALF * h + CW * b; c < HALF * h + CW * b + CW; ++c) local_step(c, chk);
+                for (int c = HALF * h + CW * b; c < HALF * h + CW * b + CW; ++c) local_step(c, chk, fwd);
             }
+        }
+        if (h == 0) {
+            // workgroup 0's steps are all checked: post the verdict on them,
+            // and store this workgroup's half of Q (the search rewrites it)
+            const bool bad0 = __syncthreads_or(viol);
+            if (t == 0) st_agent_i(verdict0, bad0 ? 1 : 0);
+            store_q();
         }
     }
     __builtin_amdgcn_s_setprio(0);
+    if (h == 0) store_up(z_early);
     const bool bad = __syncthreads_or(viol || !ok);
+    // Workgroup 1 stores U' and Q (and Z when the input is separate) before
+    // the decision when every step of the panel passed its check: they then
+    // equal what the search would write, bit for bit, so it does not matter
+    // whether they land before or after the search's own stores.
+    __shared__ int early_s;
 
     // verdict and decision
     __shared__ int commit_s;
+    if (h == 1) {
+        if (t == 0) {
+            st_agent_i(verdict1, bad ? 1 : 0);
+            int v = -1;
+            for (int spins = 0; !bad && spins < kDuoSpin; ++spins) {
+                v = ld_agent_i(verdict0);
+                if (v >= 0) break;
+                __builtin_amdgcn_s_sleep(8);
+            }
+            early_s = !bad && v == 0;
+        }
+        __syncthreads();
+        if (early_s) {
+            store_q();
+            store_up(z_early);
+        }
+    }
     if (t == 0) {
         if (h == 1) {
-            st_agent_i(verdict1, bad ? 1 : 0);
             int d = -1;
             for (int spins = 0; spins < kDuoDecideSpin; ++spins) {
                 d = ld_agent_i(decision);
@@ -1127,22 +1201,12 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
     __syncthreads();
     if (!commit_s) return false;
 
-#pragma unroll
-    for (int r = 0; r < QPT; ++r) {
-        const int e = h * qhalf + t + NT * r, c = e % nb, j = e / nb;
-        const int gj = j < k0 ? j : j + nb;
-        if (t + NT * r < qhalf && e < qtot) a.Q[c + (int64_t)gj * nb] = qv[r];
+    if (h == 1 && !early_s) {
+        store_q();
+        store_up(true);
+    } else if (!z_early) {
+        store_z();
     }
-#pragma unroll
-    for (int i = 0; i < RR; ++i)
-#pragma unroll
-        for (int j = 0; j < CW; ++j) {
-            const int row = rowr[i], col = HALF * h + CW * w + j;
-            if (row < L) {
-                a.Up[row + (int64_t)col * L] = z[i][j] - ((row == k0 + col) ? 1.0 : 0.0);
-                a.Z[row + (int64_t)(k0 + col) * a.ldz] = z[i][j];
-            }
-        }
     if (h == 0) {
         for (int c = t; c < nb; c += NT) a.rsel[k0 + c] = k0 + c;
         for (int row = t; row < L; row += NT) {
@@ -1163,6 +1227,10 @@ __global__ void __launch_bounds__(512) leaf_duo(LeafArgs a) {
         if (wpanel_duo<4>(a)) return;
         if (blockIdx.x != 0) return;
         if (threadIdx.x == 0) *a.spec = 0;
+        // the stores made before the decision are complete before the search
+        // rewrites the same outputs
+        __threadfence();
+        __syncthreads();
     } else if (blockIdx.x != 0) {
         return;
     }
@@ -1381,10 +1449,20 @@ __global__ void __launch_bounds__(256)
     Z[i + (int64_t)j * L] = (double)in[i + (int64_t)j * ldi];
 }
 
+// out[rinv[i]][rsel[c]] = Z[i][c].  When xg is given, also fills the leaf's
+// exchange areas for the two-workgroup panels of the next leaf (nd doubles
+// with the pattern, ni decision words with -1); the leaf's panels have all
+// completed when this kernel runs.
 template <typename TO>
 __global__ void __launch_bounds__(256)
     leaf_unpermute(const double *__restrict__ Z, int L, const int *__restrict__ rsel,
-                   TO *__restrict__ out, int64_t ldo) {
+                   TO *__restrict__ out, int64_t ldo, double *__restrict__ xg, int nd,
+                   int *__restrict__ xc, int ni) {
+    if (xg) {
+        for (int e = blockIdx.x * 256 + threadIdx.x; e < nd; e += gridDim.x * 256)
+            xg[e] = __longlong_as_double((long long)kDuoPoison);
+        if (blockIdx.x == 0 && (int)threadIdx.x < ni) xc[threadIdx.x] = -1;
+    }
     __shared__ int rinv[kLeafMaxOrder];
     for (int k = threadIdx.x; k < L; k += 256) rinv[k] = -1;
     __syncthreads();
@@ -1451,29 +1529,31 @@ hipError_t panel_launch(const PanelArgs &pa, hipStream_t s) {
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Leaves of order 129 .. 256 run their full panels on two workgroups
-// (leaf_duo), with an exchange area per panel.
+// (leaf_duo), with an exchange area per panel.  The areas sit at the start
+// of every blocked leaf's scratch, so that leaves of every order find them at
+// the same place and no other leaf writes them.
 constexpr int kDuoPanels = 4;
+constexpr int kDuoDoubles = kDuoPanels * duo_panel_doubles<4>();
+constexpr int kDuoInts = kDuoPanels * kDuoPanelInts;
+static_assert(kDuoInts <= 256, "the decision words are filled by one workgroup");
 bool duo_leaf(int64_t L) { return L > 128 && L <= 256; }
-size_t duo_bytes(int64_t L) {
-    return duo_leaf(L) ? align256(sizeof(double) * kDuoPanels * duo_panel_doubles<4>()) +
-                             align256(sizeof(int) * kDuoPanels * kDuoPanelInts)
-                       : 0;
-}
+size_t duo_bytes() { return align256(sizeof(double) * kDuoDoubles) + align256(sizeof(int) * kDuoInts); }
 
 }  // namespace
 
 size_t leaf_scratch_bytes(int64_t L) {
     if (L <= 128) return 0;
     const int64_t nb = panel_width(L);
-    return align256(sizeof(double) * L * L) + align256(sizeof(double) * L * nb) +
-           align256(sizeof(double) * L * nb) + align256(sizeof(int) * L) +
-           align256(sizeof(int) * L) + duo_bytes(L);
+    return duo_bytes() + align256(sizeof(double) * L * L) + align256(sizeof(double) * L * nb) +
+           align256(sizeof(double) * L * nb) + align256(sizeof(int) * L) + align256(sizeof(int) * L);
 }
+
+bool leaf_fills_exchange(int64_t L) { return duo_leaf(L); }
 
 hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DType out_dt,
                        int64_t ldo, int64_t L64, int64_t col0, int *status, void *scratch,
-                       hipStream_t s, void (*trace_cb)(void *, const LaunchInfo &, int),
-                       void *trace_ctx) {
+                       bool exch_filled, hipStream_t s,
+                       void (*trace_cb)(void *, const LaunchInfo &, int), void *trace_ctx) {
     if (L64 < 1 || L64 > kLeafMaxOrder) return hipErrorInvalidValue;
     const int L = (int)L64;
     const double Ld = (double)L;
@@ -1507,6 +1587,10 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
     if (!scratch) return hipErrorInvalidValue;
     const int nb = panel_width(L);
     char *p = static_cast<char *>(scratch);
+    double *const xg = reinterpret_cast<double *>(p);
+    p += align256(sizeof(double) * kDuoDoubles);
+    int *const xc = reinterpret_cast<int *>(p);
+    p += align256(sizeof(int) * kDuoInts);
     double *Z = reinterpret_cast<double *>(p);
     p += align256(sizeof(double) * L * L);
     double *Up = reinterpret_cast<double *>(p);
@@ -1517,17 +1601,12 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
     p += align256(sizeof(int) * L);
     int *used = reinterpret_cast<int *>(p);
     p += align256(sizeof(int) * L);
-    double *xg = nullptr;
-    int *xc = nullptr;
-    if (duo_leaf(L)) {
-        xg = reinterpret_cast<double *>(p);
-        p += align256(sizeof(double) * kDuoPanels * duo_panel_doubles<4>());
-        xc = reinterpret_cast<int *>(p);
-        LaunchInfo li{"leaf_duo_reset", 0.0, 8.0 * kDuoPanels * duo_panel_doubles<4>()};
+    const bool duo = duo_leaf(L);
+    if (duo && !exch_filled) {
+        LaunchInfo li{"leaf_duo_reset", 0.0, 8.0 * kDuoDoubles};
         cb(li, 0);
-        const int64_t nd = (int64_t)kDuoPanels * duo_panel_doubles<4>();
-        hipLaunchKernelGGL(leaf_duo_reset, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, s, xg, nd,
-                           xc, kDuoPanels * kDuoPanelInts);
+        hipLaunchKernelGGL(leaf_duo_reset, dim3((unsigned)((kDuoDoubles + 255) / 256)), dim3(256), 0, s,
+                           xg, (int64_t)kDuoDoubles, xc, kDuoInts);
         hipError_t e = hipGetLastError();
         cb(li, 1);
         if (e != hipSuccess) return e;
@@ -1576,7 +1655,7 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                 la.rsel = rsel;
                 la.Up = Up;
                 la.Q = Q;
-                if (duo_leaf(L) && w == 64 && k0 % 64 == 0 && k0 / 64 < kDuoPanels) {
+                if (duo && w == 64 && k0 % 64 == 0 && k0 / 64 < kDuoPanels) {
                     la.xg = xg + (int64_t)(k0 / 64) * duo_panel_doubles<4>();
                     la.xc = xc + (k0 / 64) * kDuoPanelInts;
                     hipLaunchKernelGGL(leaf_duo, dim3(2), dim3(512), 0, s, la);
@@ -1623,15 +1702,18 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
         if (e != hipSuccess) return e;
     }
     {
-        LaunchInfo li{"leaf_unpermute", 0.0, (out_dt == kF64 ? 16.0 : 12.0) * Ld * Ld};
+        LaunchInfo li{"leaf_unpermute", 0.0,
+                      (out_dt == kF64 ? 16.0 : 12.0) * Ld * Ld + (duo ? 8.0 * kDuoDoubles : 0.0)};
         cb(li, 0);
         const int gb = nblk < 1024 ? nblk : 1024;
+        // a two-workgroup leaf leaves its exchange areas filled for the next
+        double *fxg = duo ? xg : nullptr;
         if (out_dt == kF64)
             hipLaunchKernelGGL((leaf_unpermute<double>), dim3(gb), dim3(256), 0, s, Z, L, rsel,
-                               static_cast<double *>(out), ldo);
+                               static_cast<double *>(out), ldo, fxg, kDuoDoubles, xc, kDuoInts);
         else
             hipLaunchKernelGGL((leaf_unpermute<float>), dim3(gb), dim3(256), 0, s, Z, L, rsel,
-                               static_cast<float *>(out), ldo);
+                               static_cast<float *>(out), ldo, fxg, kDuoDoubles, xc, kDuoInts);
         hipError_t e = hipGetLastError();
         cb(li, 1);
         return e;

@@ -506,6 +506,7 @@ inline void *at(const Exec &E, const Ref &r) {
 }
 
 hipError_t run_plan(const Plan &P, const Exec &E) {
+    bool exch_filled = false;  // the leaf scratch's exchange areas (leaf_launch)
     for (size_t i = 0; i < P.ops.size(); ++i) {
         const POp &op = P.ops[i];
         TraceCtx ctx{E.s, op.level, nullptr};
@@ -556,9 +557,10 @@ hipError_t run_plan(const Plan &P, const Exec &E) {
             if (e != hipSuccess) return e;
         } else {
             hipError_t e = leaf_launch(at(E, op.in), E.dt, op.in.ld, at(E, op.out), E.dt,
-                                       op.out.ld, op.L, op.col0, E.status, E.leaf_scratch, E.s,
-                                       tr ? trace_cb : nullptr, &ctx);
+                                       op.out.ld, op.L, op.col0, E.status, E.leaf_scratch,
+                                       exch_filled, E.s, tr ? trace_cb : nullptr, &ctx);
             if (e != hipSuccess) return e;
+            exch_filled = exch_filled || leaf_fills_exchange(op.L);
         }
     }
     return hipSuccess;

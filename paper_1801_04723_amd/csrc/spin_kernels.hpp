@@ -70,13 +70,21 @@ hipError_t gemm_launch(const GemmProb *probs, int count, DType dt, hipStream_t s
 //   in  : order-L block, element type `in_dt`, leading dimension ldi
 //   out : order-L block, element type `out_dt`, leading dimension ldo
 //   status : device int, atomically lowered to col0 + k + 1 on a failing pivot
-//   scratch: FP64 scratch for the blocked tier (leaf_scratch_bytes(L) bytes)
+//   scratch: FP64 scratch for the blocked tier (leaf_scratch_bytes(L) bytes);
+//            it starts with the exchange areas of the two-workgroup panels
+//   exch_filled: those areas already hold their fill pattern, because the
+//            last leaf_launch on this scratch, earlier on the same stream, was
+//            for an order with leaf_fills_exchange() true and no other leaf or
+//            kernel has written the scratch since; otherwise (always safe)
+//            a leaf that needs them fills them first
 size_t leaf_scratch_bytes(int64_t L);
-// Number of kernel launches leaf_launch() issues for order L (tracing aid).
 hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DType out_dt,
                        int64_t ldo, int64_t L, int64_t col0, int *status, void *scratch,
-                       hipStream_t s, void (*trace_cb)(void *, const LaunchInfo &, int),
-                       void *trace_ctx);
+                       bool exch_filled, hipStream_t s,
+                       void (*trace_cb)(void *, const LaunchInfo &, int), void *trace_ctx);
+// True when leaf_launch() for order L leaves the exchange areas filled at its
+// end.  Leaves of other orders leave them as they found them.
+bool leaf_fills_exchange(int64_t L);
 
 // Whole leaves of order <= 128 from independent requests, one workgroup each,
 // in one launch (per leaf size class); each leaf's result is identical to the

@@ -121,6 +121,7 @@ struct Request {
     char *ws = nullptr;
     std::vector<Step> steps;
     size_t next = 0;
+    bool exch_filled = false;  // the leaf scratch's exchange areas (leaf_launch)
     hipEvent_t done = nullptr;
 };
 
@@ -435,7 +436,8 @@ int spin_server_tick(spin_server *s, spin_stream_t stream) {
             } else {
                 e = leaf_launch(stp.leaf.in, stp.dt, stp.leaf.ldi, stp.leaf.out, stp.dt,
                                 stp.leaf.ldo, stp.leaf.L, stp.leaf.col0, stp.leaf.status,
-                                stp.leaf_scratch, st, nullptr, nullptr);
+                                stp.leaf_scratch, r->exch_filled, st, nullptr, nullptr);
+                if (e == hipSuccess && leaf_fills_exchange(stp.leaf.L)) r->exch_filled = true;
             }
             ++r->next;
             break;
