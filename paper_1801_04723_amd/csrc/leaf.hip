@@ -1471,13 +1471,16 @@ __global__ void __launch_bounds__(256)
         if ((unsigned)r < (unsigned)L) rinv[r] = k;
     }
     __syncthreads();
-    const int64_t total = (int64_t)L * L;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * 256) {
-        const int i = (int)(e % L), c = (int)(e / L);
-        const int ri = rinv[i], rc = rsel[c];
-        if ((unsigned)ri < (unsigned)L && (unsigned)rc < (unsigned)L)
-            out[ri + (int64_t)rc * ldo] = (TO)Z[e];
+    // one column per workgroup at a time
+    for (int c = blockIdx.x; c < L; c += gridDim.x) {
+        const int rc = rsel[c];
+        if ((unsigned)rc >= (unsigned)L) continue;
+        const double *zc = Z + (int64_t)c * L;
+        TO *oc = out + (int64_t)rc * ldo;
+        for (int i = threadIdx.x; i < L; i += 256) {
+            const int ri = rinv[i];
+            if ((unsigned)ri < (unsigned)L) oc[ri] = (TO)zc[i];
+        }
     }
 }
 
@@ -1705,7 +1708,7 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
         LaunchInfo li{"leaf_unpermute", 0.0,
                       (out_dt == kF64 ? 16.0 : 12.0) * Ld * Ld + (duo ? 8.0 * kDuoDoubles : 0.0)};
         cb(li, 0);
-        const int gb = nblk < 1024 ? nblk : 1024;
+        const int gb = L < 1024 ? L : 1024;
         // a two-workgroup leaf leaves its exchange areas filled for the next
         double *fxg = duo ? xg : nullptr;
         if (out_dt == kF64)

@@ -64,9 +64,14 @@ def _same_bits(x, y):
 
 
 # diagonal pivots all the way (speculation holds) and a late off-diagonal
-# pivot (speculation fails at step k and the block is redone by the search)
-LEAF_CASES = [(L, None) for L in (1, 17, 64, 100, 128, 129, 256, 300, 512)] + \
-             [(64, 40), (128, 126), (256, 150), (256, 3), (512, 300)]
+# pivot (speculation fails at step k and the block is redone by the search).
+# Leaves of order 129-256 run their full 64-column panels on two workgroups,
+# each owning 32 of the panel's steps: the failing step falls in the first
+# workgroup's half (3, 150) or the second's (40, 100, 170, 254), in the first
+# panel (read from the input) or a later one (read from the leaf's copy).
+LEAF_CASES = [(L, None) for L in (1, 17, 64, 100, 128, 129, 200, 256, 300, 512)] + \
+             [(64, 40), (128, 126), (256, 150), (256, 3), (256, 40), (256, 100), (200, 170),
+              (256, 254), (512, 300)]
 
 
 @pytest.mark.parametrize("L,swap", LEAF_CASES)
@@ -87,10 +92,14 @@ def test_single_leaf_spec_equals_search(torch_cuda, L, swap):
 
 
 @pytest.mark.parametrize("n,leaf,swap", [(1024, 256, None), (1024, 256, 300), (1024, 128, 5),
-                                         (1000, 64, 700), (2048, 512, 1100)])
+                                         (1000, 64, 700), (2048, 512, 1100), (1100, 512, None),
+                                         (1100, 512, 936), (600, 300, None)])
 def test_inversion_spec_equals_search(torch_cuda, n, leaf, swap):
     """A whole recursion; with a swap, an early leaf speculates successfully and
-    the leaf holding the swapped rows fails its check."""
+    the leaf holding the swapped rows fails its check.  n = 1100 with leaf 512
+    has leaves of orders 320, 256, 320 and 204, and n = 600 with leaf 300
+    leaves of orders 192, 128 and 280, so the two-workgroup panels' exchange
+    areas pass across leaves of other tiers and orders."""
     import paper_1801_04723_amd as S
     torch = torch_cuda
     A = W.diag_dominant(n, seed=n + leaf)
@@ -131,17 +140,18 @@ def test_batch_spec_equals_search(torch_cuda):
     assert _same_bits(x0, x1)
 
 
-@pytest.mark.parametrize("L", [64, 256])
-def test_breakdown_reported_the_same(torch_cuda, L):
-    """A zero row and column: both ways report the same 1-based column."""
+@pytest.mark.parametrize("L,z", [(64, 20), (256, 20), (256, 45), (200, 150)])
+def test_breakdown_reported_the_same(torch_cuda, L, z):
+    """A zero row and column: both ways report the same 1-based column (for
+    order 256 and 200 in either workgroup's half of a two-workgroup panel)."""
     import paper_1801_04723_amd as S
     torch = torch_cuda
     A = W.diag_dominant(L, seed=5)
-    A[:, 20] = 0.0
-    A[20, :] = 0.0
+    A[:, z] = 0.0
+    A[z, :] = 0.0
     dA = _dev(torch, A)
     _, s0, _, s1 = _both(lambda: S.invert(dA, leaf=L))
-    assert s0 == s1 == 21
+    assert s0 == s1 == z + 1
     A = W.diag_dominant(L, seed=6)
     A[7, 3] = np.nan
     dA = _dev(torch, A)
