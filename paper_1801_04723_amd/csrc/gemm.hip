@@ -613,6 +613,160 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
     }
 }
 
+// Large products on the BF16 matrix cores: eight waves share a 256 x 256
+// tile (128 x 64 per wave), for products of at least 256 such tiles with
+// 16-byte aligned rows of whole float4 vectors.  A 32-deep slab carries twice
+// the flops per byte of FP32 operands loaded that the 128 x 128 tile does,
+// and each wave issues 32 matrix instructions between two barriers instead
+// of 16, which covers more of the next slab's load latency.  Staging
+// (rounding, swizzled k chunks) and epilogue are gemm_bf16's (plain BF16
+// only: bf16x3 keeps the 128 x 128 tile, whose hi and lo planes fit two
+// workgroups per CU).
+template <int BM, int BN, int WM, int WN, int NG>
+__global__ void __launch_bounds__(512, 1) gemm_bf16_big(GroupArgs<NG> g) {
+    constexpr int BK = 32;
+    constexpr int NT = 512;
+    constexpr int WAVES_M = BM / WM;
+    static_assert(WAVES_M * (BN / WN) == 8, "eight waves per workgroup");
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int LDK = BK + 8;            // LDS pitch (elements) of one m or n row
+    constexpr int KPA = BM * BK / NT / 4;  // k per thread in the A slab (4 rows each)
+    constexpr int TPC = NT / BN;           // threads per column of the B slab
+    constexpr int KPB = BK / TPC;          // k per thread in the B slab
+    static_assert(KPA >= 1 && KPB % 8 == 0, "slab/thread mismatch");
+    typedef typename BfVec<KPA>::type va_t;
+    auto swz = [](int row) { return (row >> 4) & 3; };
+
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][BM * LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * LDK];
+
+    const int bid = blockIdx.x;
+    const int pi = group_member(g, bid);
+    const GemmProb P = g.p[pi];
+    const int tstart = g.tile_start[pi], tiles_m = g.tiles_m[pi];
+    int tm, tn;
+    tile_coords(bid - tstart, tstart, tiles_m, (P.n + BN - 1) / BN, false, tm, tn);
+    const int M = P.m, N = P.n, K = P.k;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const float *__restrict__ A = static_cast<const float *>(P.A);
+    const float *__restrict__ B = static_cast<const float *>(P.B);
+    const int64_t lda = P.lda, ldb = P.ldb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave % WAVES_M) * WM, wn0 = (wave / WAVES_M) * WN;
+
+    // A slab: rows 4*mq .. 4*mq+3, k = kq*KPA .. kq*KPA + KPA-1
+    const int mq = tid % (BM / 4), kq = tid / (BM / 4);
+    const int am = m0 + 4 * mq;
+    // B slab: column bn, k = bk .. bk + KPB-1
+    const int bn = tid / TPC, bk = (tid % TPC) * KPB;
+    const int bcol = n0 + bn;
+
+    float ra[KPA][4], rb[KPB];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < KPA; ++j) {
+            const int k = k0 + kq * KPA + j;
+            const bool ok = am < M && k < K;
+            const float4 x = *reinterpret_cast<const float4 *>(ok ? A + am + (int64_t)k * lda : A);
+            ra[j][0] = ok ? x.x : 0.f;
+            ra[j][1] = ok ? x.y : 0.f;
+            ra[j][2] = ok ? x.z : 0.f;
+            ra[j][3] = ok ? x.w : 0.f;
+        }
+#pragma unroll
+        for (int h = 0; h < KPB / 4; ++h) {
+            const int k = k0 + bk + 4 * h;
+            const bool ok = bcol < N && k < K;
+            const float4 x = *reinterpret_cast<const float4 *>(ok ? B + k + (int64_t)bcol * ldb : B);
+            rb[4 * h + 0] = ok ? x.x : 0.f;
+            rb[4 * h + 1] = ok ? x.y : 0.f;
+            rb[4 * h + 2] = ok ? x.z : 0.f;
+            rb[4 * h + 3] = ok ? x.w : 0.f;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            va_t hi;
+#pragma unroll
+            for (int j = 0; j < KPA; ++j) hi[j] = (__bf16)ra[j][i];
+            const int row = 4 * mq + i, k = kq * KPA;
+            *reinterpret_cast<va_t *>(&As[buf][row * LDK + (((k >> 3) ^ swz(row)) << 3) + (k & 7)]) = hi;
+        }
+#pragma unroll
+        for (int h0 = 0; h0 < KPB; h0 += 8) {
+            bf8_t hi;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) hi[j] = (__bf16)rb[h0 + j];
+            const int k = bk + h0;
+            *reinterpret_cast<bf8_t *>(&Bs[buf][bn * LDK + (((k >> 3) ^ swz(bn)) << 3) + (k & 7)]) = hi;
+        }
+    };
+
+    f4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+
+    const int g4 = lane >> 4, c16 = lane & 15;
+    auto compute = [&](int buf) {
+        bf8_t b[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int row = wn0 + 16 * j + c16;
+            b[j] = *reinterpret_cast<const bf8_t *>(&Bs[buf][row * LDK + ((g4 ^ swz(row)) << 3)]);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int row = wm0 + 16 * i + c16;
+            const bf8_t a = *reinterpret_cast<const bf8_t *>(&As[buf][row * LDK + ((g4 ^ swz(row)) << 3)]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[j], a, acc[i][j], 0, 0, 0);
+        }
+    };
+
+    const int KT = (K + BK - 1) / BK;
+    if (KT > 0) {
+        gload(0);
+        sstore(0);
+        __syncthreads();
+        for (int kt = 0; kt + 1 < KT; ++kt) {
+            gload((kt + 1) * BK);
+            compute(kt & 1);
+            sstore((kt & 1) ^ 1);
+            __syncthreads();
+        }
+        compute((KT - 1) & 1);
+    }
+
+    const float *__restrict__ C0 = static_cast<const float *>(P.C0);
+    float *D = static_cast<float *>(P.D);
+    float *DT = static_cast<float *>(P.DT);
+    const double alpha = P.alpha, beta = P.beta;
+    const bool use_c = (beta != 0.0) && (C0 != nullptr);
+    const bool add_i = P.add_identity != 0;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int gm = m0 + wm0 + i * 16 + c16;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gn = n0 + wn0 + j * 16 + 4 * g4 + v;
+                if (gm < M && gn < N) {
+                    double val = alpha * (double)acc[i][j][v];
+                    if (use_c) val += beta * (double)C0[gm + (int64_t)gn * P.ldc];
+                    if (add_i && gm == gn) val += 1.0;
+                    D[gm + (int64_t)gn * P.ldd] = (float)val;
+                    if (DT != nullptr) DT[gn + (int64_t)gm * P.lddt] = (float)val;
+                }
+            }
+        }
+    }
+}
+
 // Tile prefix sums of up to N products for a BM x BN tiling; returns the
 // number of workgroups.
 template <int BM, int BN, int N>
@@ -662,6 +816,15 @@ hipError_t launch_bf16_group(const GemmProb *probs, int count, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int BM, int BN, int WM, int WN, int N>
+hipError_t launch_bf16_big_group(const GemmProb *probs, int count, hipStream_t s) {
+    GroupArgs<N> g;
+    const int total = make_group<BM, BN, N>(probs, count, g);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL((gemm_bf16_big<BM, BN, WM, WN, N>), dim3(total), dim3(512), 0, s, g);
+    return hipGetLastError();
+}
+
 // K slab of the fast 128x128 kernel (FP64: 16 keeps two workgroups per CU;
 // FP32: 32).  Every other fast configuration uses 32.
 constexpr int kFastBK128 = 16;
@@ -671,7 +834,7 @@ constexpr int fast_bk(int tile, int es) { return (tile == 128 && es == 8) ? kFas
 // shape, leading dimensions and alignment), so that a product is computed
 // bit for bit the same whether it is launched alone or grouped with others.
 struct Cfg {
-    int tile;   // 128, 64 or 32
+    int tile;   // 128, 64 or 32; 256 for the eight-wave BF16 tiles
     bool fast;  // branch-free vector path
     bool operator==(const Cfg &o) const { return tile == o.tile && fast == o.fast; }
 };
@@ -695,6 +858,10 @@ Cfg choose_cfg(const GemmProb &p, DType dt) {
     if (dt == kBF16 || dt == kBF16X3) {
         // float4 loads along m (A) and along k (B)
         c.fast = p.m % 4 == 0 && p.k % 4 == 0 && p.lda % 4 == 0 && p.ldb % 4 == 0 && aligned;
+        // plain BF16: eight-wave 256 x 256 tiles once they alone fill the
+        // GPU; not for the lower-triangle mode
+        const int64_t big = ((p.m + 255) / 256) * ((p.n + 255) / 256);
+        if (dt == kBF16 && c.fast && !p.lower && big >= 256) c.tile = 256;
         return c;
     }
     const int bk = fast_bk(c.tile, es);
@@ -718,6 +885,8 @@ hipError_t launch_cfg(Cfg c, const GemmProb *probs, int count, hipStream_t s) {
 
 template <bool X3, int N>
 hipError_t launch_cfg_bf16(Cfg c, const GemmProb *probs, int count, hipStream_t s) {
+    if constexpr (!X3)
+        if (c.tile == 256) return launch_bf16_big_group<256, 256, 128, 64, N>(probs, count, s);
     if (c.tile == 128)
         return c.fast ? launch_bf16_group<128, 128, 64, 64, X3, true, N>(probs, count, s)
                       : launch_bf16_group<128, 128, 64, 64, X3, false, N>(probs, count, s);
@@ -740,6 +909,7 @@ const char *cfg_name(Cfg c, DType dt) {
         {{"gemm_bf16x3_128x128_edge", "gemm_bf16x3_128x128"},
          {"gemm_bf16x3_64x64_edge", "gemm_bf16x3_64x64"},
          {"gemm_bf16x3_32x32_edge", "gemm_bf16x3_32x32"}}};
+    if (c.tile == 256) return "gemm_bf16_256x256";
     const int ti = c.tile == 128 ? 0 : c.tile == 64 ? 1 : 2;
     return names[(int)dt][ti][c.fast ? 1 : 0];
 }

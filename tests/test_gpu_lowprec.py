@@ -48,9 +48,13 @@ def _host(t):
 
 
 # m % 4, k % 4 and the leading dimensions decide between the vector and the
-# guarded kernel; the tile count decides between 128, 64 and 32 tiles.
+# guarded kernel; the tile count decides between 128, 64 and 32 tiles, and,
+# for plain BF16 vector products of at least 256 of them, the eight-wave
+# 256 x 256 tile (the last two shapes, the last with ragged edges and a
+# partial k slab).
 SHAPES = [(64, 64, 64), (200, 136, 300), (130, 70, 45), (33, 17, 5), (1, 1, 1),
-          (512, 512, 512), (2048, 1536, 96), (2050, 1540, 99), (2048, 2048, 64)]
+          (512, 512, 512), (2048, 1536, 96), (2050, 1540, 99), (2048, 2048, 64),
+          (4096, 4096, 64), (4100, 4104, 100)]
 
 
 @pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
