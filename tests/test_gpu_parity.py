@@ -62,6 +62,10 @@ GEMM_CASES = [
     # 128-tile kernel: 16 x 16 tiles take the XCD block order, 16 x 12 the plain order
     (2048, 2048, 64, -1.0, 1.0, False, 0),
     (2048, 1536, 100, 1.0, 1.0, False, 3),
+    # eight waves per workgroup: 128-tile with 240 tiles and a ragged n; 64-tile
+    # with ragged m and n
+    (1920, 2040, 96, -1.0, 1.0, False, 2),
+    (1000, 1100, 64, 1.0, 1.0, False, 4),
     (40, 40, 0, -1.0, 1.0, True, 0),
 ]
 
@@ -103,7 +107,8 @@ def test_gemm_in_place_c0_equals_d(torch_cuda):
     assert np.all(np.abs(_host(dC) - ref) <= bound)
 
 
-@pytest.mark.parametrize("m,n,k", [(64, 64, 64), (200, 136, 300), (512, 512, 512)])
+@pytest.mark.parametrize("m,n,k", [(64, 64, 64), (200, 136, 300), (512, 512, 512), (1024, 1000, 96),
+                                   (2048, 1920, 64)])
 def test_gemm_f32_parity(torch_cuda, m, n, k):
     import paper_1801_04723_amd as S
     torch = torch_cuda
