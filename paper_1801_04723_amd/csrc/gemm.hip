@@ -252,9 +252,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(GroupArgs<NG> g) {
 // (any assignment of k to the four MFMA k-slots is valid as long as A and B
 // agree).  B is staged k-contiguous (Bs[n][k]) so that a lane fetches its KQ
 // B values with 16-byte LDS reads; A is staged m-contiguous (As[k][m]).
-// NW waves per workgroup, two workgroups per CU: four for the 128 x 128 and
-// 32 x 32 tiles, eight (32 x 16 each) for the 64 x 64 tile, whose products of
-// 256 tiles would otherwise leave one wave per SIMD.
+// NW waves per workgroup, two workgroups per CU: eight for the 128 x 128
+// tile (64 x 32 each) and the 64 x 64 tile (32 x 16 each), four for the
+// 32 x 32 tile.  Eight waves put four on each SIMD (two when a product
+// leaves one workgroup per CU), so more of the slab loads and barriers hide
+// behind other waves' matrix instructions.
 template <int BM, int BN, int BK, int WM, int WN, typename T, int NG, int NW>
 __global__ void __launch_bounds__(64 * NW, NW / 2) gemm_fast(GroupArgs<NG> g) {
     constexpr int NT = 64 * NW;
@@ -837,10 +839,9 @@ constexpr int fast_bk(int tile, int es) { return (tile == 128 && es == 8) ? kFas
 // shape, leading dimensions and alignment), so that a product is computed
 // bit for bit the same whether it is launched alone or grouped with others.
 struct Cfg {
-    int tile;       // 128, 64 or 32; 256 for the eight-wave BF16 tiles
-    bool fast;      // branch-free vector path
-    int waves = 4;  // of a fast 128 x 128 tile: 8 for products of at most 256 tiles
-    bool operator==(const Cfg &o) const { return tile == o.tile && fast == o.fast && waves == o.waves; }
+    int tile;   // 128, 64 or 32; 256 for the eight-wave BF16 tiles
+    bool fast;  // branch-free vector path
+    bool operator==(const Cfg &o) const { return tile == o.tile && fast == o.fast; }
 };
 
 Cfg choose_cfg(const GemmProb &p, DType dt) {
@@ -871,19 +872,14 @@ Cfg choose_cfg(const GemmProb &p, DType dt) {
     const int bk = fast_bk(c.tile, es);
     c.fast = p.k > 0 && p.k % bk == 0 && p.m % vw == 0 && p.lda % vw == 0 && p.ldb % vw == 0 &&
              aligned;
-    // a product of at most 256 128-tiles gives one workgroup per CU: eight
-    // waves then keep two per SIMD
-    if (c.fast && c.tile == 128 && t128 <= 256) c.waves = 8;
     return c;
 }
 
 template <typename T, int N>
 hipError_t launch_cfg(Cfg c, const GemmProb *probs, int count, hipStream_t s) {
     constexpr int ES = sizeof(T);
-    if (c.tile == 128 && c.fast && c.waves == 8)
-        return launch_group<true, 128, 128, fast_bk(128, ES), 64, 32, T, N, 8>(probs, count, s);
     if (c.tile == 128)
-        return c.fast ? launch_group<true, 128, 128, fast_bk(128, ES), 64, 64, T, N>(probs, count, s)
+        return c.fast ? launch_group<true, 128, 128, fast_bk(128, ES), 64, 32, T, N, 8>(probs, count, s)
                       : launch_group<false, 128, 128, 16, 64, 64, T, N>(probs, count, s);
     if (c.tile == 64)
         return c.fast ? launch_group<true, 64, 64, fast_bk(64, ES), 32, 16, T, N, 8>(probs, count, s)
@@ -919,7 +915,6 @@ const char *cfg_name(Cfg c, DType dt) {
          {"gemm_bf16x3_64x64_edge", "gemm_bf16x3_64x64"},
          {"gemm_bf16x3_32x32_edge", "gemm_bf16x3_32x32"}}};
     if (c.tile == 256) return "gemm_bf16_256x256";
-    if (c.tile == 128 && c.waves == 8) return dt == kF64 ? "gemm_f64_128x128_w8" : "gemm_f32_128x128_w8";
     const int ti = c.tile == 128 ? 0 : c.tile == 64 ? 1 : 2;
     return names[(int)dt][ti][c.fast ? 1 : 0];
 }
