@@ -38,6 +38,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <cstdlib>
 
 #include "spin_kernels.hpp"
 
@@ -120,9 +121,12 @@ struct LeafArgs {
     // that the later leaves of the same inversion go straight to the search.
     int *spec;
     // Two-workgroup panels: this panel's exchange area (multipliers and
-    // pivots of its 64 steps) and its verdict and decision words.
+    // inverse pivots of its 64 steps), its verdict and decision words, and
+    // the number of polls after which a wait for the other workgroup gives
+    // up (and the panel falls back to the search).
     double *xg;
     int *xc;
+    int duo_spin;
 };
 
 template <int TR, int RR, int RC, bool WHOLE, typename TI, typename TO>
@@ -883,7 +887,7 @@ __device__ __attribute__((always_inline)) inline bool wpanel_pipe(const LeafArgs
 // equal to the pattern in the input only makes a wait run out, which aborts
 // to the search.
 constexpr unsigned long long kDuoPoison = 0x7FF4DEADBEEF0001ull;  // a signalling NaN
-constexpr int kDuoSpin = 1 << 15;        // polls of a data wait (about 64 clocks each and more)
+constexpr int kDuoSpin = 1 << 15;        // default polls of a data wait (about 64 clocks each and more)
 constexpr int kDuoDecideSpin = 1 << 24;  // polls of workgroup 1's wait for the decision
 
 __device__ inline double ld_agent(const double *p) {
@@ -1097,7 +1101,7 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
                 double tf[RR], tp;
                 int spins = 0;
                 do {
-                    if (++spins > kDuoSpin) return false;
+                    if (++spins > a.duo_spin) return false;
                     __builtin_amdgcn_s_sleep(2);
                     load(c, tf, tp);
                 } while (missing(tf, tp));
@@ -1164,7 +1168,7 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
         if (t == 0) {
             st_agent_i(verdict1, bad ? 1 : 0);
             int v = -1;
-            for (int spins = 0; !bad && spins < kDuoSpin; ++spins) {
+            for (int spins = 0; !bad && spins < a.duo_spin; ++spins) {
                 v = ld_agent_i(verdict0);
                 if (v >= 0) break;
                 __builtin_amdgcn_s_sleep(8);
@@ -1188,7 +1192,7 @@ __device__ __attribute__((always_inline)) inline bool wpanel_duo(const LeafArgs 
             commit_s = d == 1;
         } else {
             int v = -1;
-            for (int spins = 0; !bad && spins < kDuoSpin; ++spins) {
+            for (int spins = 0; !bad && spins < a.duo_spin; ++spins) {
                 v = ld_agent_i(verdict1);
                 if (v >= 0) break;
                 __builtin_amdgcn_s_sleep(8);
@@ -1540,6 +1544,14 @@ constexpr int kDuoDoubles = kDuoPanels * duo_panel_doubles<4>();
 constexpr int kDuoInts = kDuoPanels * kDuoPanelInts;
 static_assert(kDuoInts <= 256, "the decision words are filled by one workgroup");
 bool duo_leaf(int64_t L) { return L > 128 && L <= 256; }
+// Polls after which a two-workgroup panel gives up waiting for the other
+// workgroup: kDuoSpin, or SPIN_DUO_SPIN (a positive count; small values make
+// the panels fall back to the search, for tests of that path).
+int duo_spin_limit() {
+    const char *e = std::getenv("SPIN_DUO_SPIN");
+    const long v = e ? std::strtol(e, nullptr, 10) : 0;
+    return (v > 0 && v <= kDuoSpin) ? (int)v : kDuoSpin;
+}
 size_t duo_bytes() { return align256(sizeof(double) * kDuoDoubles) + align256(sizeof(int) * kDuoInts); }
 
 }  // namespace
@@ -1661,6 +1673,7 @@ hipError_t leaf_launch(const void *in, DType in_dt, int64_t ldi, void *out, DTyp
                 if (duo && w == 64 && k0 % 64 == 0 && k0 / 64 < kDuoPanels) {
                     la.xg = xg + (int64_t)(k0 / 64) * duo_panel_doubles<4>();
                     la.xc = xc + (k0 / 64) * kDuoPanelInts;
+                    la.duo_spin = duo_spin_limit();
                     hipLaunchKernelGGL(leaf_duo, dim3(2), dim3(512), 0, s, la);
                     e = hipGetLastError();
                 } else if (L <= 256)

@@ -157,3 +157,34 @@ def test_breakdown_reported_the_same(torch_cuda, L, z):
     dA = _dev(torch, A)
     _, s0, _, s1 = _both(lambda: S.invert(dA, leaf=L))
     assert s0 == s1 and s0 > 0
+
+
+@pytest.mark.parametrize("n,leaf", [(256, 256), (200, 256), (1024, 256)])
+@pytest.mark.parametrize("spin", [1, 4])
+def test_two_workgroup_panels_give_up_to_the_search(torch_cuda, n, leaf, spin):
+    """Panels of leaves of order 129-256 run on two workgroups that wait for
+    each other a bounded number of polls.  With that bound forced down
+    (SPIN_DUO_SPIN) the waits run out, the panel falls back to the search, and
+    the inverse is still the search's bit for bit (eager launches, so that no
+    cached graph keeps the default bound)."""
+    import paper_1801_04723_amd as S
+    torch = torch_cuda
+    A = W.diag_dominant(n, seed=n + spin)
+    dA = _dev(torch, A)
+    keys = ("SPIN_DUO_SPIN", "SPIN_NO_GRAPH")
+    old = {k: os.environ.get(k) for k in keys}
+    try:
+        os.environ["SPIN_NO_GRAPH"] = "1"
+        os.environ["SPIN_DUO_SPIN"] = str(spin)
+        x0, s0, x1, s1 = _both(lambda: S.invert(dA, leaf=leaf))
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    assert s0 == s1 == 0
+    assert _same_bits(x0, x1)
+    ref, info = oracle.strassen_inv(A, leaf)
+    assert info == 0
+    assert np.linalg.norm(x1 - ref) / np.linalg.norm(ref) <= 1e-13
