@@ -428,12 +428,12 @@ struct BfVec {
     typedef __bf16 type __attribute__((ext_vector_type(KN)));
 };
 
-template <int BM, int BN, int WM, int WN, bool X3, bool VEC, int NG>
-__global__ void __launch_bounds__(256, 2) gemm_bf16(GroupArgs<NG> g) {
+template <int BM, int BN, int WM, int WN, bool X3, bool VEC, int NG, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, NW / 2) gemm_bf16(GroupArgs<NG> g) {
     constexpr int BK = 32;
-    constexpr int NT = 256;
+    constexpr int NT = 64 * NW;
     constexpr int WAVES_M = BM / WM;
-    static_assert(WAVES_M * (BN / WN) == 4, "four waves per workgroup");
+    static_assert(WAVES_M * (BN / WN) == NW, "NW waves per workgroup");
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int LDK = BK + 8;           // LDS pitch (elements) of one m or n row
     constexpr int KPA = BM * BK / NT / 4;  // k per thread in the A slab (4 rows each)
@@ -812,12 +812,12 @@ hipError_t launch_group(const GemmProb *probs, int count, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int BM, int BN, int WM, int WN, bool X3, bool VEC, int N>
+template <int BM, int BN, int WM, int WN, bool X3, bool VEC, int N, int NW = 4>
 hipError_t launch_bf16_group(const GemmProb *probs, int count, hipStream_t s) {
     GroupArgs<N> g;
     const int total = make_group<BM, BN, N>(probs, count, g);
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL((gemm_bf16<BM, BN, WM, WN, X3, VEC, N>), dim3(total), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_bf16<BM, BN, WM, WN, X3, VEC, N, NW>), dim3(total), dim3(64 * NW), 0, s, g);
     return hipGetLastError();
 }
 
@@ -893,7 +893,7 @@ hipError_t launch_cfg_bf16(Cfg c, const GemmProb *probs, int count, hipStream_t 
     if constexpr (!X3)
         if (c.tile == 256) return launch_bf16_big_group<256, 256, 128, 64, N>(probs, count, s);
     if (c.tile == 128)
-        return c.fast ? launch_bf16_group<128, 128, 64, 64, X3, true, N>(probs, count, s)
+        return c.fast ? launch_bf16_group<128, 128, 64, 32, X3, true, N, 8>(probs, count, s)
                       : launch_bf16_group<128, 128, 64, 64, X3, false, N>(probs, count, s);
     if (c.tile == 64)
         return c.fast ? launch_bf16_group<64, 64, 32, 32, X3, true, N>(probs, count, s)
