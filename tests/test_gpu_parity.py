@@ -66,6 +66,10 @@ GEMM_CASES = [
     # with ragged m and n
     (1920, 2040, 96, -1.0, 1.0, False, 2),
     (1000, 1100, 64, 1.0, 1.0, False, 4),
+    # 32-tile products with several K slabs: a ragged m and n, and a k that
+    # is a multiple of 64 but not of 128
+    (96, 130, 256, -1.0, 1.0, False, 2),
+    (200, 64, 192, 1.0, 0.0, False, 0),
     (40, 40, 0, -1.0, 1.0, True, 0),
 ]
 
