@@ -34,6 +34,15 @@
  *              most 64 graphs are kept (the cache is emptied when full, after
  *              waiting for the device).  The environment variable
  *              SPIN_NO_GRAPH=1 makes every call launch its kernels directly.
+ *   Leaves     two further environment variables change how a leaf is
+ *              eliminated but never its result: SPIN_NO_SPEC=1 runs the pivot
+ *              search at every step instead of first trying the diagonal
+ *              pivots and verifying them; SPIN_DUO_SPIN=<count> lowers the
+ *              bound on each wait of a panel eliminated by two workgroups
+ *              (a wait that runs out sends the panel to the one-workgroup
+ *              search).  Both are read when a call is enqueued, and a graph
+ *              recorded earlier keeps the setting it was recorded with, so
+ *              set them before the first call or with SPIN_NO_GRAPH=1.
  *   Errors     the return value is an argument or resource status known at
  *              enqueue time: 0 = enqueued, negative = SPIN_E_* (nothing was
  *              enqueued).  The numerical status (a zero or non-finite leaf
